@@ -1,0 +1,224 @@
+/*
+ * fdfb.h -- C ABI of the MI355X full-domain functional bootstrapping library.
+ *
+ * The library computes the full-domain functional bootstrap of Kluczniak &
+ * Schild (arXiv 2109.02731, Sec. 3.2, Fig. 2 "Bootstrap") over LWE / RLWE
+ * samples with ciphertext modulus q = Q = 2^32: every coefficient is a
+ * uint32_t and arithmetic wraps mod 2^32.  The GLWE rank is 1 (RLWE).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: 0 on success or a negative FDFB_E* code.  No entry point
+ *    aborts the process; the text of the last error of the calling thread is
+ *    returned by fdfb_last_error().
+ *  - LWE samples are stored [b, a_1 .. a_d] (b first, Sec. 2 Def. "Generalized
+ *    Learning With Errors"), row-major, one row per sample.
+ *  - RLWE samples are stored [b_0 .. b_{N-1}, a_0 .. a_{N-1}].
+ *  - "d_" pointers are device (HBM) pointers owned by the caller, valid on the
+ *    given stream; "host" pointers are ordinary host memory.  `stream` is a
+ *    hipStream_t passed as void* (NULL = the null stream).  Device work is
+ *    enqueued asynchronously on `stream`; the call returns once it is queued.
+ *  - A context (fdfb_ctx) owns the evaluation keys in device memory and the
+ *    secret keys in host memory (for the *_debug calls).  Calls on one
+ *    context must not overlap from several threads; distinct contexts are
+ *    independent.
+ *  - Results are bit-identical for identical inputs whatever the batch size,
+ *    batch composition, kernel form (batched or plain) or stream.
+ */
+#ifndef FDFB_H
+#define FDFB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDFB_OK 0
+#define FDFB_EINVAL (-1)   /* invalid argument or parameter set            */
+#define FDFB_ENOMEM (-2)   /* host or device allocation failed             */
+#define FDFB_EDEVICE (-3)  /* a HIP runtime call failed (text in last_error) */
+#define FDFB_EABORTED (-4) /* the host abort flag was raised               */
+#define FDFB_ENOTSUP (-5)  /* parameter set not supported by the kernels   */
+
+/* flags of fdfb_bootstrap_batch / fdfb_blind_rotate */
+#define FDFB_OUT_EXTRACTED 0x1u /* return c_Q (dimension N, key s_F) instead of
+                                   the key-switched sample (Sec. 3.4, "Computing
+                                   in Z_t": affine maps on c_Q before switching) */
+#define FDFB_PLAIN 0x2u         /* run the plain one-sample-per-workgroup
+                                   VALU kernels instead of the batched MFMA ones */
+
+/*
+ * Parameter set.  q = Q = 2^32 is fixed.  Gadget bases are powers of two,
+ * L = 2^log2B; when ell*log2B < 32 the gadget is g_j = 2^(32-ell*log2B) L^(j-1)
+ * and values are rounded (half up) to their top ell*log2B bits before the
+ * unsigned digit decomposition (Sec. 2 Def. "Decomposition").
+ *   n, N      LWE dimension and ring degree (N a power of two, 256..2048)
+ *   log2_t    plaintext modulus t = 2^log2_t, t <= 2N
+ *   g_*       blind-rotation key gadget (L_RGSW)
+ *   ks_*      key switching key LWE(s_F, N) -> LWE(s, n)
+ *   pk_*      packing key LWE(s_F, N) -> RLWE(s_F)
+ *   boot_*    public-mux digits: base L_boot, ell_boot = ceil(log_Lboot t)
+ *   sigma_*   noise standard deviations in units of 1 (q = 2^32): fresh LWE
+ *             samples, blind-rotation key, packing key, key switching key
+ */
+typedef struct fdfb_params {
+    uint32_t n, N, log2_t;
+    uint32_t g_log2B, g_ell;
+    uint32_t ks_log2B, ks_ell;
+    uint32_t pk_log2B, pk_ell;
+    uint32_t boot_log2B, boot_ell;
+    double sigma_lwe, sigma_glwe, sigma_pk, sigma_ks;
+} fdfb_params;
+
+typedef struct fdfb_ctx fdfb_ctx;
+
+/*
+ * Key generation from a 64-bit seed (Sec. 3.2 Theorem "Correctness of the
+ * Bootstrapping": brK = BRKeyGen(s, 𝔰), pK = KeySwitchSetup(s_F -> 𝔰),
+ * ksK = KeySwitchSetup(s_F -> s); App. A Figs. "BRKeyGen", "KeySwitchSetup").
+ * Secrets s in {0,1}^n and 𝔰 in {0,1}^N are uniform binary; s_F = Coefs(𝔰).
+ * Randomness: counter-based SplitMix64 (one stream per purpose) and rounded
+ * Box-Muller Gaussians; the exact stream layout is fixed so that any
+ * implementation of the same definition reproduces the keys bit for bit.
+ * Host only: no device memory is touched until the first device call.
+ * On success *out owns the new context (release with fdfb_free).
+ * Errors: FDFB_EINVAL for an unsupported parameter set, FDFB_ENOMEM.
+ */
+int fdfb_keygen_from_seed(const fdfb_params *params, uint64_t seed, fdfb_ctx **out);
+
+/*
+ * Register a lookup table f: Z_t -> Z_t (host array table[t], values in
+ * [0, t)) and build its rotation polynomials rotP_0, rotP_1 (Sec. 3.3,
+ * Fig. 2 "SetupPolynomial"; the table is stored unscaled, Delta = 2^32/t is
+ * applied once inside the public mux).  *lut_id receives a small index
+ * (0, 1, 2, ...) used by fdfb_bootstrap_batch.  Errors: FDFB_EINVAL when a
+ * value is >= t, FDFB_ENOMEM.
+ */
+int fdfb_register_lut(fdfb_ctx *ctx, const uint32_t *table, int32_t *lut_id);
+
+/*
+ * Full-domain functional bootstrap of B LWE samples (Sec. 3.2, Fig. 2):
+ * ModSwitch to Z_2N; ell_boot sign blind rotations; SampleExtract;
+ * BuildAcc = packing key switch + public mux of rotP_1 X^b / rotP_0 X^b
+ * (Sec. 3.1, Fig. 1); the function blind rotation; SampleExtract; the final
+ * key switch (ModSwitch Q -> q is the identity since Q = q).
+ *   d_cts      device uint32[B][n+1], inputs under s
+ *   d_lut_ids  device int32[B], each a registered lut_id
+ *   d_out      device uint32[B][n+1] (under s), or uint32[B][N+1] (under
+ *              s_F) when FDFB_OUT_EXTRACTED is set
+ *   flags      FDFB_OUT_EXTRACTED | FDFB_PLAIN
+ * Scratch memory is taken from a pool owned by the context and grown on
+ * demand (hipMalloc) the first time a larger B is seen.  B = 0 is a no-op.
+ * Errors: FDFB_EINVAL (null pointer with B > 0), FDFB_ENOMEM, FDFB_EDEVICE.
+ * lut_ids are validated on the device: an out-of-range id yields all-zero
+ * output for that sample.
+ */
+int fdfb_bootstrap_batch(fdfb_ctx *ctx, const uint32_t *d_cts, const int32_t *d_lut_ids,
+                         uint32_t B, uint32_t *d_out, uint32_t flags, void *stream);
+
+/* One job of fdfb_bootstrap_multi: a batch on its own context (its own
+ * parameter set, e.g. a different N). */
+typedef struct fdfb_job {
+    fdfb_ctx *ctx;
+    const uint32_t *d_cts;
+    const int32_t *d_lut_ids;
+    uint32_t B;
+    uint32_t *d_out;
+    uint32_t flags;
+} fdfb_job;
+
+/*
+ * Bootstrap several jobs (mixed parameter sets and lookup tables) as one
+ * stream-ordered submission.  Equivalent, output for output, to calling
+ * fdfb_bootstrap_batch on each job.  Errors as fdfb_bootstrap_batch.
+ */
+int fdfb_bootstrap_multi(const fdfb_job *jobs, uint32_t njobs, void *stream);
+
+/*
+ * LWE -> LWE key switch with ksK (App. A Fig. "KeySwitch"):
+ * d_in uint32[B][N+1] under s_F -> d_out uint32[B][n+1] under s.
+ */
+int fdfb_keyswitch(fdfb_ctx *ctx, const uint32_t *d_in, uint32_t B, uint32_t *d_out, void *stream);
+
+/* ---- single procedures of the path, for tests and custom pipelines ----- */
+
+/* ModSwitch(ct, q, 2N) of every coordinate (App. A Fig. "ModSwitch"):
+ * d_cts uint32[B][n+1] -> d_ctN uint32[B][n+1] with values in [0, 2N). */
+int fdfb_modswitch(fdfb_ctx *ctx, const uint32_t *d_cts, uint32_t B, uint32_t *d_ctN, void *stream);
+
+/*
+ * BlindRotate (App. A Fig. "Blind Rotation", u = {1}): for every accumulator
+ * a in [A], acc_a <- CMux(brK[i], acc_a X^(-a_i), acc_a) for i = 1..n, where
+ * a_i comes from row (a / accs_per_ct) of d_ctN.  d_acc uint32[A][2][N] is
+ * updated in place; d_ctN uint32[A/accs_per_ct][n+1] (values in [0, 2N)).
+ * flags: FDFB_PLAIN selects the VALU kernel.
+ */
+int fdfb_blind_rotate(fdfb_ctx *ctx, uint32_t *d_acc, const uint32_t *d_ctN, uint32_t A,
+                      uint32_t accs_per_ct, uint32_t flags, void *stream);
+
+/* SampleExtract(acc, 1) (App. A Fig. "SampleExtract"):
+ * d_acc uint32[A][2][N] -> d_lwe uint32[A][N+1]. */
+int fdfb_sample_extract(fdfb_ctx *ctx, const uint32_t *d_acc, uint32_t A, uint32_t *d_lwe,
+                        void *stream);
+
+/* LWE -> RLWE key switch with the packing key pK (App. A Fig. "KeySwitch"):
+ * d_in uint32[A][N+1] under s_F -> d_out uint32[A][2][N] under 𝔰. */
+int fdfb_packing_keyswitch(fdfb_ctx *ctx, const uint32_t *d_in, uint32_t A, uint32_t *d_out,
+                           void *stream);
+
+/*
+ * PubMux (Sec. 3.1 Fig. 1) of the bootstrap: for every sample b,
+ * acc_b = [Delta p_A, 0] + sum_i digit_i((p_B - p_A) mod t) * R_{b,i} with
+ * p_A = rotP_1 X^(b_N), p_B = rotP_0 X^(b_N) of lut d_lut_ids[b] and b_N the
+ * first entry of row b of d_ctN.  d_rlwe uint32[B][ell_boot][2][N],
+ * d_acc uint32[B][2][N].
+ */
+int fdfb_pubmux(fdfb_ctx *ctx, const uint32_t *d_rlwe, const uint32_t *d_ctN,
+                const int32_t *d_lut_ids, uint32_t B, uint32_t *d_acc, void *stream);
+
+/* ---- debug helpers (host memory, use the secret keys) ------------------ */
+
+/* Encrypt B messages m[b] in [0, t) under s: b = <a, s> + Delta m + e with a
+ * uniform and e ~ round(N(0, sigma_lwe^2)) drawn from `seed` (sample b uses
+ * counter range b).  cts_host uint32[B][n+1]. */
+int fdfb_encrypt_debug(fdfb_ctx *ctx, const uint32_t *m, uint32_t B, uint64_t seed,
+                       uint32_t *cts_host);
+
+/* Decrypt B samples of dimension dim (n: key s; N: key s_F):
+ * m_out[b] = round(t * phase / 2^32) mod t (Sec. 1.2 "Regev Encryption");
+ * err_out (nullable) receives the centred error phase - Delta m. */
+int fdfb_decrypt_debug(fdfb_ctx *ctx, const uint32_t *cts_host, uint32_t B, uint32_t dim,
+                       uint32_t *m_out, int64_t *err_out);
+
+/*
+ * Serialise the context (parameters, seed, secrets, raw keys and registered
+ * tables) into buf.  *len: in = capacity of buf, out = bytes needed.  With
+ * buf == NULL only the size is reported.  Errors: FDFB_EINVAL when the
+ * capacity is too small.
+ */
+int fdfb_export_keys(const fdfb_ctx *ctx, void *buf, size_t *len);
+
+/* Rebuild a context from fdfb_export_keys output.  Errors: FDFB_EINVAL for
+ * a malformed or truncated buffer. */
+int fdfb_import_keys(const void *buf, size_t len, fdfb_ctx **out);
+
+/* Copy one raw key array to host memory (for key-equality checks):
+ * which = 0 s [n], 1 s_F [N], 2 brK [n][2 g_ell][2][N], 3 pK [N][pk_ell][2][N],
+ * 4 ksK [N][ks_ell][n+1].  *count: in = capacity (words), out = words needed. */
+int fdfb_get_key(const fdfb_ctx *ctx, uint32_t which, uint32_t *host, size_t *count);
+
+/* Raise or clear the abort flag; while raised, device entry points return
+ * FDFB_EABORTED without enqueuing work. */
+void fdfb_set_abort(fdfb_ctx *ctx, int raised);
+
+/* Release a context and its device memory (NULL is a no-op). */
+void fdfb_free(fdfb_ctx *ctx);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *fdfb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDFB_H */

@@ -1,0 +1,256 @@
+"""MI355X full-domain functional bootstrapping (FDFB, arXiv 2109.02731).
+
+Thin ctypes binding over ``libfdfb.so`` (C ABI in ``include/fdfb.h``).  The
+binding only marshals arguments: every step of the bootstrap runs in the
+library's HIP kernels.  PyTorch supplies device memory and streams: device
+arguments are torch tensors (int32 or uint32 storage, contiguous, on the GPU)
+and work is enqueued on the current torch stream unless one is given.
+
+If the shared library is missing it is built once with hipcc; if that fails
+the import fails -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from ._build import LIB as _LIB_PATH, build as _build
+
+OUT_EXTRACTED = 0x1
+PLAIN = 0x2
+
+FDFB_OK = 0
+_ERRNAMES = {-1: "FDFB_EINVAL", -2: "FDFB_ENOMEM", -3: "FDFB_EDEVICE", -4: "FDFB_EABORTED",
+             -5: "FDFB_ENOTSUP"}
+
+
+class FdfbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("N", C.c_uint32), ("log2_t", C.c_uint32),
+                ("g_log2B", C.c_uint32), ("g_ell", C.c_uint32),
+                ("ks_log2B", C.c_uint32), ("ks_ell", C.c_uint32),
+                ("pk_log2B", C.c_uint32), ("pk_ell", C.c_uint32),
+                ("boot_log2B", C.c_uint32), ("boot_ell", C.c_uint32),
+                ("sigma_lwe", C.c_double), ("sigma_glwe", C.c_double),
+                ("sigma_pk", C.c_double), ("sigma_ks", C.c_double)]
+
+
+class _Job(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("d_cts", C.c_void_p), ("d_lut_ids", C.c_void_p),
+                ("B", C.c_uint32), ("d_out", C.c_void_p), ("flags", C.c_uint32)]
+
+
+EXPORTED = [
+    "fdfb_keygen_from_seed", "fdfb_register_lut", "fdfb_bootstrap_batch", "fdfb_bootstrap_multi",
+    "fdfb_keyswitch", "fdfb_modswitch", "fdfb_blind_rotate", "fdfb_sample_extract",
+    "fdfb_packing_keyswitch", "fdfb_pubmux", "fdfb_encrypt_debug", "fdfb_decrypt_debug",
+    "fdfb_export_keys", "fdfb_import_keys", "fdfb_get_key", "fdfb_set_abort", "fdfb_free",
+    "fdfb_last_error",
+]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            _build()
+        L = C.CDLL(_LIB_PATH)
+        P, u32, u64, sz = C.c_void_p, C.c_uint32, C.c_uint64, C.c_size_t
+        i = C.c_int
+        sigs = {
+            "fdfb_keygen_from_seed": (i, [P, u64, P]),
+            "fdfb_register_lut": (i, [P, P, P]),
+            "fdfb_bootstrap_batch": (i, [P, P, P, u32, P, u32, P]),
+            "fdfb_bootstrap_multi": (i, [P, u32, P]),
+            "fdfb_keyswitch": (i, [P, P, u32, P, P]),
+            "fdfb_modswitch": (i, [P, P, u32, P, P]),
+            "fdfb_blind_rotate": (i, [P, P, P, u32, u32, u32, P]),
+            "fdfb_sample_extract": (i, [P, P, u32, P, P]),
+            "fdfb_packing_keyswitch": (i, [P, P, u32, P, P]),
+            "fdfb_pubmux": (i, [P, P, P, P, u32, P, P]),
+            "fdfb_encrypt_debug": (i, [P, P, u32, u64, P]),
+            "fdfb_decrypt_debug": (i, [P, P, u32, u32, P, P]),
+            "fdfb_export_keys": (i, [P, P, C.POINTER(sz)]),
+            "fdfb_import_keys": (i, [P, sz, P]),
+            "fdfb_get_key": (i, [P, u32, P, C.POINTER(sz)]),
+            "fdfb_set_abort": (None, [P, i]),
+            "fdfb_free": (None, [P]),
+            "fdfb_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sigs.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != FDFB_OK:
+        raise FdfbError(rc, lib().fdfb_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t, what: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a GPU torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.element_size() != 4:
+        raise TypeError(f"{what} must have 32-bit elements")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def params_struct(p) -> _Params:
+    d = p.as_dict() if hasattr(p, "as_dict") else dict(p)
+    return _Params(**{k: d[k] for k, _ in _Params._fields_})
+
+
+class Context:
+    """Evaluation keys (device) and secret keys (host) of one parameter set."""
+
+    def __init__(self, handle: C.c_void_p, params):
+        self._h = handle
+        self.params = params
+
+    # ---- construction --------------------------------------------------
+    @classmethod
+    def keygen(cls, params, seed: int) -> "Context":
+        h = C.c_void_p()
+        ps = params_struct(params)
+        _check(lib().fdfb_keygen_from_seed(C.byref(ps), seed, C.byref(h)))
+        return cls(h, params)
+
+    @classmethod
+    def import_keys(cls, blob: bytes, params=None) -> "Context":
+        h = C.c_void_p()
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().fdfb_import_keys(buf, len(blob), C.byref(h)))
+        return cls(h, params)
+
+    def export_keys(self) -> bytes:
+        n = C.c_size_t(0)
+        _check(lib().fdfb_export_keys(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().fdfb_export_keys(self._h, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def free(self):
+        if self._h:
+            lib().fdfb_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # ---- host-side helpers ----------------------------------------------
+    def get_key(self, which: int) -> np.ndarray:
+        n = C.c_size_t(0)
+        _check(lib().fdfb_get_key(self._h, which, None, C.byref(n)))
+        out = np.empty(n.value, np.uint32)
+        _check(lib().fdfb_get_key(self._h, which, _np_ptr(out), C.byref(n)))
+        return out
+
+    def register_lut(self, table) -> int:
+        tab = np.ascontiguousarray(table, dtype=np.uint32)
+        lid = C.c_int32()
+        _check(lib().fdfb_register_lut(self._h, _np_ptr(tab), C.byref(lid)))
+        return lid.value
+
+    def encrypt_debug(self, msgs, seed: int) -> np.ndarray:
+        m = np.ascontiguousarray(msgs, dtype=np.uint32).reshape(-1)
+        out = np.empty((m.size, self.params.n + 1), np.uint32)
+        _check(lib().fdfb_encrypt_debug(self._h, _np_ptr(m), m.size, seed, _np_ptr(out)))
+        return out
+
+    def decrypt_debug(self, cts) -> tuple[np.ndarray, np.ndarray]:
+        cts = np.ascontiguousarray(np.atleast_2d(cts), dtype=np.uint32)
+        B, width = cts.shape
+        m = np.empty(B, np.uint32)
+        e = np.empty(B, np.int64)
+        _check(lib().fdfb_decrypt_debug(self._h, _np_ptr(cts), B, width - 1, _np_ptr(m), _np_ptr(e)))
+        return m, e
+
+    def set_abort(self, raised: bool):
+        lib().fdfb_set_abort(self._h, 1 if raised else 0)
+
+    # ---- device entry points (torch tensors) ------------------------------
+    def bootstrap_batch(self, cts, lut_ids, out, flags: int = 0, stream=None):
+        B = int(cts.shape[0]) if cts.dim() > 1 else 0
+        _check(lib().fdfb_bootstrap_batch(self._h, _dev_ptr(cts, "cts"), _dev_ptr(lut_ids, "lut_ids"), B,
+                                          _dev_ptr(out, "out"), flags, _stream(stream)))
+        return out
+
+    def keyswitch(self, d_in, out, stream=None):
+        _check(lib().fdfb_keyswitch(self._h, _dev_ptr(d_in, "in"), int(d_in.shape[0]),
+                                    _dev_ptr(out, "out"), _stream(stream)))
+        return out
+
+    def modswitch(self, cts, out, stream=None):
+        _check(lib().fdfb_modswitch(self._h, _dev_ptr(cts, "cts"), int(cts.shape[0]), _dev_ptr(out, "out"),
+                                    _stream(stream)))
+        return out
+
+    def blind_rotate(self, acc, ctN, accs_per_ct: int = 1, flags: int = 0, stream=None):
+        _check(lib().fdfb_blind_rotate(self._h, _dev_ptr(acc, "acc"), _dev_ptr(ctN, "ctN"), int(acc.shape[0]),
+                                       accs_per_ct, flags, _stream(stream)))
+        return acc
+
+    def sample_extract(self, acc, out, stream=None):
+        _check(lib().fdfb_sample_extract(self._h, _dev_ptr(acc, "acc"), int(acc.shape[0]), _dev_ptr(out, "out"),
+                                         _stream(stream)))
+        return out
+
+    def packing_keyswitch(self, d_in, out, stream=None):
+        _check(lib().fdfb_packing_keyswitch(self._h, _dev_ptr(d_in, "in"), int(d_in.shape[0]),
+                                            _dev_ptr(out, "out"), _stream(stream)))
+        return out
+
+    def pubmux(self, rlwe, ctN, lut_ids, out, stream=None):
+        _check(lib().fdfb_pubmux(self._h, _dev_ptr(rlwe, "rlwe"), _dev_ptr(ctN, "ctN"),
+                                 _dev_ptr(lut_ids, "lut_ids"), int(out.shape[0]), _dev_ptr(out, "out"),
+                                 _stream(stream)))
+        return out
+
+
+def bootstrap_multi(jobs, stream=None):
+    """jobs: list of (Context, cts, lut_ids, out, flags)."""
+    arr = (_Job * max(1, len(jobs)))()
+    for k, (ctx, cts, ids, out, flags) in enumerate(jobs):
+        arr[k] = _Job(ctx._h, _dev_ptr(cts, "cts").value, _dev_ptr(ids, "lut_ids").value, int(cts.shape[0]),
+                      _dev_ptr(out, "out").value, flags)
+    _check(lib().fdfb_bootstrap_multi(arr, len(jobs), _stream(stream)))
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    """uint32 numpy array -> int32 torch tensor with the same bits."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    """32-bit torch tensor -> uint32 numpy array with the same bits."""
+    return t.detach().cpu().contiguous().numpy().view(np.uint32)

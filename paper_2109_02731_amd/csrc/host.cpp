@@ -1,0 +1,684 @@
+// Host core of the FDFB library: parameter checks, seeded key generation,
+// rotation polynomials, device key layouts, scratch pool and the stream-
+// ordered orchestration of the bootstrap (Sec. 3.2, Fig. 2 "Bootstrap").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fdfb.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            return fail(FDFB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));      \
+    } while (0)
+
+// --------------------------------------------------------------------------
+// Counter-based SplitMix64 (Steele, Lea & Flood, OOPSLA 2014; finaliser of
+// Vigna's reference splitmix64.c).  Stream `tag` of seed `seed` starts at
+// state fin(seed + tag * gamma); its k-th output is fin(state + (k+1) gamma).
+// --------------------------------------------------------------------------
+class CounterRng {
+  public:
+    static constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+    CounterRng(uint64_t seed, uint64_t tag) : state0_(fin(seed + tag * kGamma)) {}
+    uint64_t word(uint64_t k) const { return fin(state0_ + (k + 1) * kGamma); }
+    uint32_t uniform32(uint64_t k) const { return static_cast<uint32_t>(word(k) >> 32); }
+    uint32_t bit(uint64_t k) const { return static_cast<uint32_t>(word(k) >> 63); }
+    // Rounded N(0, sigma^2): Box-Muller on outputs 2k and 2k+1.
+    int64_t gaussian(uint64_t k, double sigma) const
+    {
+        if (sigma == 0.0) return 0;
+        const double u1 = static_cast<double>((word(2 * k) >> 11) + 1) * (1.0 / 9007199254740992.0);
+        const double u2 = static_cast<double>(word(2 * k + 1) >> 11) * (1.0 / 9007199254740992.0);
+        const double z = std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+        return static_cast<int64_t>(std::nearbyint(z * sigma));
+    }
+
+  private:
+    static uint64_t fin(uint64_t z)
+    {
+        z ^= z >> 30;
+        z *= 0xBF58476D1CE4E5B9ull;
+        z ^= z >> 27;
+        z *= 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    uint64_t state0_;
+};
+
+enum StreamTag : uint64_t {
+    kTagS = 1, kTagSF = 2, kTagBrkA = 3, kTagBrkE = 4, kTagPkA = 5, kTagPkE = 6,
+    kTagKsA = 7, kTagKsE = 8, kTagEncA = 9, kTagEncE = 10
+};
+
+inline uint32_t gadget_word(uint32_t log2B, uint32_t ell, uint32_t j)
+{
+    return 1u << (32 - ell * log2B + log2B * j);
+}
+
+unsigned worker_count()
+{
+    unsigned h = std::thread::hardware_concurrency();
+    return std::max(1u, std::min(h ? h : 1u, 16u));
+}
+
+template <class F>
+void parallel_for(size_t count, F &&f)
+{
+    const unsigned nt = worker_count();
+    if (count < 2 || nt == 1) {
+        for (size_t k = 0; k < count; ++k) f(k);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    std::vector<std::thread> pool;
+    for (unsigned w = 0; w < nt; ++w)
+        pool.emplace_back([&] {
+            for (size_t k; (k = next.fetch_add(1)) < count;) f(k);
+        });
+    for (auto &th : pool) th.join();
+}
+
+// b <- a * sf + noise with binary sf: a sum of negacyclic rotations of a.
+void times_binary_key(const uint32_t *a, const std::vector<uint32_t> &sf, uint32_t N, uint32_t *b)
+{
+    for (uint32_t p = 0; p < N; ++p) {
+        if (!sf[p]) continue;
+        for (uint32_t m = 0; m < p; ++m) b[m] -= a[m + N - p];
+        for (uint32_t m = p; m < N; ++m) b[m] += a[m - p];
+    }
+}
+
+// Balanced signed byte limbs of a 32-bit word: w = sum_l limb_l 256^l mod 2^32.
+inline void balanced_limbs(uint32_t w, int8_t out[4])
+{
+    int64_t v = w;
+    for (int l = 0; l < 4; ++l) {
+        const int64_t lo = ((v & 0xFF) ^ 0x80) - 0x80;
+        out[l] = static_cast<int8_t>(lo);
+        v = (v - lo) >> 8;
+    }
+}
+
+}  // namespace
+
+// ============================================================================
+// context
+// ============================================================================
+struct fdfb_ctx {
+    fdfb_params P{};
+    uint64_t seed = 0;
+    std::vector<uint32_t> s, sf, brk, pk, ksk;
+    std::vector<uint32_t> lut_tables;  // [nluts][t]
+    std::vector<int32_t> lut_polys;    // [nluts][2][N]: rotP_0, rotP_1
+    int nluts = 0;
+
+    fdfbk::Geometry geom{};
+    bool mfma_ok = false;
+
+    bool on_device = false;
+    uint32_t *d_brk = nullptr, *d_pk = nullptr, *d_ksk = nullptr;
+    void *d_brk_frag = nullptr;
+    int32_t *d_luts = nullptr;
+    int dev_nluts = 0;
+
+    uint32_t cap = 0;  // scratch capacity in samples
+    uint32_t *d_ctN = nullptr, *d_acc_sign = nullptr, *d_cbits = nullptr, *d_rbits = nullptr,
+             *d_accf = nullptr, *d_cq = nullptr;
+
+    std::atomic<int> abort_flag{0};
+
+    ~fdfb_ctx() { release_device(); }
+
+    void release_device()
+    {
+        for (void *p : {(void *)d_brk, (void *)d_pk, (void *)d_ksk, d_brk_frag, (void *)d_luts,
+                        (void *)d_ctN, (void *)d_acc_sign, (void *)d_cbits, (void *)d_rbits,
+                        (void *)d_accf, (void *)d_cq})
+            if (p) (void)hipFree(p);
+        d_brk = d_pk = d_ksk = nullptr;
+        d_brk_frag = nullptr;
+        d_luts = nullptr;
+        d_ctN = d_acc_sign = d_cbits = d_rbits = d_accf = d_cq = nullptr;
+        on_device = false;
+        dev_nluts = 0;
+        cap = 0;
+    }
+};
+
+namespace {
+
+bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
+
+int check_params(const fdfb_params &P)
+{
+    if (!is_pow2(P.N) || P.N < 64 || P.N > 2048) return fail(FDFB_EINVAL, "N must be a power of two in [64, 2048]");
+    if (P.n < 1 || P.n > 4096) return fail(FDFB_EINVAL, "n must be in [1, 4096]");
+    if (P.log2_t < 1 || (1u << P.log2_t) > P.N) return fail(FDFB_EINVAL, "t must be a power of two with 2 <= t <= N");
+    struct G { uint32_t b, l; const char *name; } gs[] = {
+        {P.g_log2B, P.g_ell, "gadget"}, {P.ks_log2B, P.ks_ell, "key switch"},
+        {P.pk_log2B, P.pk_ell, "packing key"}};
+    for (auto &g : gs)
+        if (g.b < 1 || g.l < 1 || g.b * g.l > 32)
+            return fail(FDFB_EINVAL, std::string(g.name) + ": need 1 <= ell, 1 <= log2B, ell*log2B <= 32");
+    if (P.g_log2B > 14) return fail(FDFB_EINVAL, "gadget base above 2^14 is not supported");
+    if (P.ks_ell > 8 || P.pk_ell > 8) return fail(FDFB_EINVAL, "key switching ell above 8 is not supported");
+    if (P.boot_log2B < 1 || P.boot_log2B > 7 || P.boot_ell < 1 || P.boot_ell * P.boot_log2B < P.log2_t)
+        return fail(FDFB_EINVAL, "boot digits must cover t: boot_ell * boot_log2B >= log2_t, log2B in [1,7]");
+    if (!(P.sigma_lwe >= 0) || !(P.sigma_glwe >= 0) || !(P.sigma_pk >= 0) || !(P.sigma_ks >= 0))
+        return fail(FDFB_EINVAL, "noise deviations must be non-negative");
+    const uint32_t R = 2 * P.g_ell;
+    const size_t plain_lds = 8ull * P.N + 8ull * R * P.N + 4ull * R * P.N;
+    if (plain_lds > 160 * 1024) return fail(FDFB_EINVAL, "ring degree / gadget too large for the LDS");
+    return FDFB_OK;
+}
+
+fdfbk::Geometry geometry_of(const fdfb_params &P)
+{
+    fdfbk::Geometry G{};
+    G.n = P.n; G.N = P.N; G.log2_t = P.log2_t;
+    G.g_log2B = P.g_log2B; G.g_ell = P.g_ell; G.g_chunks = fdfbk::digit_chunks(P.g_log2B);
+    G.ks_log2B = P.ks_log2B; G.ks_ell = P.ks_ell;
+    G.pk_log2B = P.pk_log2B; G.pk_ell = P.pk_ell;
+    G.boot_log2B = P.boot_log2B; G.boot_ell = P.boot_ell;
+    return G;
+}
+
+// Keys of Theorem "Correctness of the Bootstrapping" (Sec. 3.2):
+//   brK[i] = RGSW(𝔰, s[i]); pK[i][j] = RLWE(𝔰, s_F[i] g_j); ksK[i][j] = LWE(s, s_F[i] g_j).
+void generate_keys(fdfb_ctx &c)
+{
+    const fdfb_params &P = c.P;
+    const uint32_t n = P.n, N = P.N, R = 2 * P.g_ell;
+    const uint64_t seed = c.seed;
+    c.s.resize(n);
+    c.sf.resize(N);
+    const CounterRng rs(seed, kTagS), rsf(seed, kTagSF);
+    for (uint32_t i = 0; i < n; ++i) c.s[i] = rs.bit(i);
+    for (uint32_t p = 0; p < N; ++p) c.sf[p] = rsf.bit(p);
+
+    c.brk.assign((size_t)n * R * 2 * N, 0);
+    const CounterRng ra(seed, kTagBrkA), re(seed, kTagBrkE);
+    parallel_for((size_t)n * R, [&](size_t row_id) {
+        const uint32_t i = row_id / R, r = row_id % R;
+        uint32_t *b = &c.brk[row_id * 2 * N], *a = b + N;
+        for (uint32_t p = 0; p < N; ++p) {
+            a[p] = ra.uniform32(row_id * N + p);
+            b[p] = static_cast<uint32_t>(re.gaussian(row_id * N + p, P.sigma_glwe));
+        }
+        times_binary_key(a, c.sf, N, b);
+        const uint32_t comp = r / P.g_ell, j = r % P.g_ell;
+        (comp == 0 ? b : a)[0] += c.s[i] * gadget_word(P.g_log2B, P.g_ell, j);
+    });
+
+    c.pk.assign((size_t)N * P.pk_ell * 2 * N, 0);
+    const CounterRng pa(seed, kTagPkA), pe(seed, kTagPkE);
+    parallel_for((size_t)N * P.pk_ell, [&](size_t row_id) {
+        const uint32_t i = row_id / P.pk_ell, j = row_id % P.pk_ell;
+        uint32_t *b = &c.pk[row_id * 2 * N], *a = b + N;
+        for (uint32_t p = 0; p < N; ++p) {
+            a[p] = pa.uniform32(row_id * N + p);
+            b[p] = static_cast<uint32_t>(pe.gaussian(row_id * N + p, P.sigma_pk));
+        }
+        times_binary_key(a, c.sf, N, b);
+        b[0] += c.sf[i] * gadget_word(P.pk_log2B, P.pk_ell, j);
+    });
+
+    c.ksk.assign((size_t)N * P.ks_ell * (n + 1), 0);
+    const CounterRng ka(seed, kTagKsA), ke(seed, kTagKsE);
+    parallel_for((size_t)N * P.ks_ell, [&](size_t row_id) {
+        const uint32_t i = row_id / P.ks_ell, j = row_id % P.ks_ell;
+        uint32_t *row = &c.ksk[row_id * (n + 1)];
+        uint32_t acc = 0;
+        for (uint32_t q = 0; q < n; ++q) {
+            row[1 + q] = ka.uniform32(row_id * n + q);
+            acc += row[1 + q] * c.s[q];
+        }
+        row[0] = acc + static_cast<uint32_t>(ke.gaussian(row_id, P.sigma_ks)) +
+                 c.sf[i] * gadget_word(P.ks_log2B, P.ks_ell, j);
+    });
+}
+
+// SetupPolynomial (Sec. 3.3, Fig. 2): windows of half-width ceil(N/t)
+// around round(2N/t) m; later writes win where windows meet.
+void setup_polynomial(const uint32_t *f, uint32_t t, uint32_t N, int32_t *p0, int32_t *p1)
+{
+    std::fill(p0, p0 + N, 0);
+    std::fill(p1, p1 + N, 0);
+    const int64_t half = (N + t - 1) / t, step = (2 * N + t / 2) / t, twoN = 2 * (int64_t)N;
+    for (uint32_t m = 0; m < t; ++m)
+        for (int64_t e = -half; e <= half; ++e) {
+            const int64_t y = ((step * m + e) % twoN + twoN) % twoN;
+            const int32_t v = static_cast<int32_t>(f[m]);
+            if (y == 0) p0[0] = v;
+            else if (y < (int64_t)N) p0[N - y] = -v;
+            else if (y == (int64_t)N) p1[0] = -v;
+            else p1[twoN - y] = v;
+        }
+}
+
+// Lane-ordered B fragments of the MFMA blind rotation: block (i, r', kb) holds,
+// for lane L and byte t, limb l of K'~[64 kb + 16 g + t + 16 s] where
+// (s, j, l) = (L/8 % 2, L/4 % 2, L % 4) of column L % 16, g = L / 16, K' the
+// key polynomial of virtual row r' (component j) times 2^(7h) for digit chunk
+// h, and K'~ its negacyclic extension.
+std::vector<int8_t> build_brk_fragments(const fdfb_ctx &c)
+{
+    const fdfb_params &P = c.P;
+    const uint32_t N = P.N, ell = P.g_ell, CH = fdfbk::digit_chunks(P.g_log2B);
+    const uint32_t RPC = ell * CH, RV = 2 * RPC, NKB = N / 64, R = 2 * ell;
+    std::vector<int8_t> out((size_t)P.n * RV * NKB * 1024);
+    parallel_for((size_t)P.n * RV, [&](size_t id) {
+        const uint32_t i = id / RV, rv = id % RV;
+        const uint32_t comp_in = rv / RPC, rr = rv % RPC, jd = rr / CH, h = rr % CH;
+        const uint32_t row = comp_in * ell + jd;
+        for (uint32_t kb = 0; kb < NKB; ++kb)
+            for (uint32_t L = 0; L < 64; ++L) {
+                const uint32_t col = L & 15, s = col >> 3, j = (col >> 2) & 1, l = col & 3, g = L >> 4;
+                const uint32_t *K = &c.brk[(((size_t)i * R + row) * 2 + j) * N];
+                int8_t *dst = &out[((id * NKB + kb) * 64 + L) * 16];
+                for (uint32_t t = 0; t < 16; ++t) {
+                    const uint32_t x = 64 * kb + 16 * g + t + 16 * s;  // < N + 16
+                    uint32_t w = (x < N) ? K[x] : 0u - K[x - N];
+                    w <<= 7 * h;
+                    int8_t limbs[4];
+                    balanced_limbs(w, limbs);
+                    dst[t] = limbs[l];
+                }
+            }
+    });
+    return out;
+}
+
+template <class T>
+int dev_upload(T **dst, const T *src, size_t count)
+{
+    if (*dst) (void)hipFree(*dst);
+    *dst = nullptr;
+    HIP_TRY(hipMalloc((void **)dst, std::max<size_t>(count, 1) * sizeof(T)));
+    if (count) HIP_TRY(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return FDFB_OK;
+}
+
+int ensure_device(fdfb_ctx &c)
+{
+    if (c.abort_flag.load()) return fail(FDFB_EABORTED, "abort flag raised");
+    if (!c.on_device) {
+        int rc;
+        if ((rc = dev_upload(&c.d_brk, c.brk.data(), c.brk.size()))) return rc;
+        if ((rc = dev_upload(&c.d_pk, c.pk.data(), c.pk.size()))) return rc;
+        if ((rc = dev_upload(&c.d_ksk, c.ksk.data(), c.ksk.size()))) return rc;
+        if (c.mfma_ok) {
+            std::vector<int8_t> fr = build_brk_fragments(c);
+            int8_t *p = nullptr;
+            if ((rc = dev_upload(&p, fr.data(), fr.size()))) return rc;
+            c.d_brk_frag = p;
+        }
+        c.on_device = true;
+    }
+    if (c.dev_nluts != c.nluts) {
+        int rc = dev_upload(&c.d_luts, c.lut_polys.data(), c.lut_polys.size());
+        if (rc) return rc;
+        c.dev_nluts = c.nluts;
+    }
+    return FDFB_OK;
+}
+
+int ensure_scratch(fdfb_ctx &c, uint32_t B)
+{
+    if (B <= c.cap) return FDFB_OK;
+    const size_t n1 = c.P.n + 1, N = c.P.N, eb = c.P.boot_ell;
+    uint32_t **bufs[] = {&c.d_ctN, &c.d_acc_sign, &c.d_cbits, &c.d_rbits, &c.d_accf, &c.d_cq};
+    const size_t words[] = {B * n1, B * eb * 2 * N, B * eb * (N + 1), B * eb * 2 * N, B * 2 * N, B * (N + 1)};
+    for (int k = 0; k < 6; ++k) {
+        if (*bufs[k]) (void)hipFree(*bufs[k]);
+        *bufs[k] = nullptr;
+    }
+    c.cap = 0;
+    for (int k = 0; k < 6; ++k) HIP_TRY(hipMalloc((void **)bufs[k], words[k] * 4));
+    c.cap = B;
+    return FDFB_OK;
+}
+
+hipError_t run_br(fdfb_ctx &c, uint32_t *acc, const uint32_t *ctN, uint32_t A, uint32_t per,
+                  uint32_t flags, hipStream_t st)
+{
+    if (!(flags & FDFB_PLAIN) && c.mfma_ok)
+        return fdfbk::launch_br_mfma(c.geom, acc, ctN, A, per, c.d_brk_frag, st);
+    return fdfbk::launch_br_plain(c.geom, acc, ctN, A, per, c.d_brk, st);
+}
+
+#define K_TRY(expr)                                                                            \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            return fail(FDFB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));      \
+    } while (0)
+
+int bootstrap_one(fdfb_ctx &c, const uint32_t *d_cts, const int32_t *d_ids, uint32_t B, uint32_t *d_out,
+                  uint32_t flags, hipStream_t st)
+{
+    int rc;
+    if ((rc = ensure_device(c))) return rc;
+    if ((rc = ensure_scratch(c, B))) return rc;
+    const fdfbk::Geometry &G = c.geom;
+    const uint32_t eb = G.boot_ell, N = G.N;
+    const uint32_t half = 1u << (31 - G.log2_t);
+    // 1. ModSwitch q -> 2N
+    K_TRY(fdfbk::launch_modswitch(G, d_cts, B, c.d_ctN, st));
+    // 2. sign accumulators and their blind rotation (one batched pass)
+    K_TRY(fdfbk::launch_init_sign(G, c.d_ctN, B, c.d_acc_sign, st));
+    K_TRY(run_br(c, c.d_acc_sign, c.d_ctN, B * eb, eb, flags, st));
+    // 3. bit samples: SampleExtract + L_boot^i Delta/2
+    K_TRY(fdfbk::launch_extract(G, c.d_acc_sign, B * eb, eb, half, c.d_cbits, st));
+    // 4. BuildAcc: LWE -> RLWE switching, then the public mux
+    K_TRY(fdfbk::launch_keyswitch(c.d_cbits, B * eb, N, c.d_pk, G.pk_log2B, G.pk_ell, 2 * N, c.d_rbits, st));
+    K_TRY(fdfbk::launch_pubmux(G, c.d_rbits, c.d_ctN, d_ids, B, c.d_luts, c.nluts, c.d_accf, st));
+    // 5. function blind rotation
+    K_TRY(run_br(c, c.d_accf, c.d_ctN, B, 1, flags, st));
+    // 6. SampleExtract, then LWE(N) -> LWE(n) unless the extracted form is requested
+    if (flags & FDFB_OUT_EXTRACTED) {
+        K_TRY(fdfbk::launch_extract(G, c.d_accf, B, 1, 0, d_out, st));
+    } else {
+        K_TRY(fdfbk::launch_extract(G, c.d_accf, B, 1, 0, c.d_cq, st));
+        K_TRY(fdfbk::launch_keyswitch(c.d_cq, B, N, c.d_ksk, G.ks_log2B, G.ks_ell, G.n + 1, d_out, st));
+    }
+    return FDFB_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char *fdfb_last_error(void) { return g_last_error.c_str(); }
+
+int fdfb_keygen_from_seed(const fdfb_params *params, uint64_t seed, fdfb_ctx **out)
+{
+    if (!params || !out) return fail(FDFB_EINVAL, "null argument");
+    *out = nullptr;
+    int rc = check_params(*params);
+    if (rc) return rc;
+    fdfb_ctx *c = new (std::nothrow) fdfb_ctx();
+    if (!c) return fail(FDFB_ENOMEM, "context allocation failed");
+    c->P = *params;
+    c->seed = seed;
+    c->geom = geometry_of(*params);
+    c->mfma_ok = fdfbk::br_mfma_supported(c->geom);
+    try {
+        generate_keys(*c);
+    } catch (const std::bad_alloc &) {
+        delete c;
+        return fail(FDFB_ENOMEM, "key allocation failed");
+    }
+    *out = c;
+    return FDFB_OK;
+}
+
+int fdfb_register_lut(fdfb_ctx *c, const uint32_t *table, int32_t *lut_id)
+{
+    if (!c || !table || !lut_id) return fail(FDFB_EINVAL, "null argument");
+    const uint32_t t = 1u << c->P.log2_t, N = c->P.N;
+    for (uint32_t m = 0; m < t; ++m)
+        if (table[m] >= t) return fail(FDFB_EINVAL, "table value out of range [0, t)");
+    c->lut_tables.insert(c->lut_tables.end(), table, table + t);
+    c->lut_polys.resize((size_t)(c->nluts + 1) * 2 * N);
+    int32_t *p = &c->lut_polys[(size_t)c->nluts * 2 * N];
+    setup_polynomial(table, t, N, p, p + N);
+    *lut_id = c->nluts++;
+    return FDFB_OK;
+}
+
+int fdfb_bootstrap_batch(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *d_lut_ids, uint32_t B,
+                         uint32_t *d_out, uint32_t flags, void *stream)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    if (c->abort_flag.load()) return fail(FDFB_EABORTED, "abort flag raised");
+    if (B == 0) return FDFB_OK;
+    if (!d_cts || !d_lut_ids || !d_out) return fail(FDFB_EINVAL, "null buffer");
+    if (flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+    return bootstrap_one(*c, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream);
+}
+
+int fdfb_bootstrap_multi(const fdfb_job *jobs, uint32_t njobs, void *stream)
+{
+    if (njobs && !jobs) return fail(FDFB_EINVAL, "null jobs");
+    for (uint32_t k = 0; k < njobs; ++k) {
+        int rc = fdfb_bootstrap_batch(jobs[k].ctx, jobs[k].d_cts, jobs[k].d_lut_ids, jobs[k].B,
+                                      jobs[k].d_out, jobs[k].flags, stream);
+        if (rc) return rc;
+    }
+    return FDFB_OK;
+}
+
+int fdfb_keyswitch(fdfb_ctx *c, const uint32_t *d_in, uint32_t B, uint32_t *d_out, void *stream)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    if (B == 0) return FDFB_OK;
+    if (!d_in || !d_out) return fail(FDFB_EINVAL, "null buffer");
+    int rc = ensure_device(*c);
+    if (rc) return rc;
+    K_TRY(fdfbk::launch_keyswitch(d_in, B, c->P.N, c->d_ksk, c->P.ks_log2B, c->P.ks_ell, c->P.n + 1, d_out,
+                                  (hipStream_t)stream));
+    return FDFB_OK;
+}
+
+int fdfb_modswitch(fdfb_ctx *c, const uint32_t *d_cts, uint32_t B, uint32_t *d_ctN, void *stream)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    if (B == 0) return FDFB_OK;
+    if (!d_cts || !d_ctN) return fail(FDFB_EINVAL, "null buffer");
+    int rc = ensure_device(*c);
+    if (rc) return rc;
+    K_TRY(fdfbk::launch_modswitch(c->geom, d_cts, B, d_ctN, (hipStream_t)stream));
+    return FDFB_OK;
+}
+
+int fdfb_blind_rotate(fdfb_ctx *c, uint32_t *d_acc, const uint32_t *d_ctN, uint32_t A,
+                      uint32_t accs_per_ct, uint32_t flags, void *stream)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    if (A == 0) return FDFB_OK;
+    if (!d_acc || !d_ctN || accs_per_ct == 0) return fail(FDFB_EINVAL, "null buffer or accs_per_ct = 0");
+    int rc = ensure_device(*c);
+    if (rc) return rc;
+    K_TRY(run_br(*c, d_acc, d_ctN, A, accs_per_ct, flags, (hipStream_t)stream));
+    return FDFB_OK;
+}
+
+int fdfb_sample_extract(fdfb_ctx *c, const uint32_t *d_acc, uint32_t A, uint32_t *d_lwe, void *stream)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    if (A == 0) return FDFB_OK;
+    if (!d_acc || !d_lwe) return fail(FDFB_EINVAL, "null buffer");
+    K_TRY(fdfbk::launch_extract(c->geom, d_acc, A, 1, 0, d_lwe, (hipStream_t)stream));
+    return FDFB_OK;
+}
+
+int fdfb_packing_keyswitch(fdfb_ctx *c, const uint32_t *d_in, uint32_t A, uint32_t *d_out, void *stream)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    if (A == 0) return FDFB_OK;
+    if (!d_in || !d_out) return fail(FDFB_EINVAL, "null buffer");
+    int rc = ensure_device(*c);
+    if (rc) return rc;
+    K_TRY(fdfbk::launch_keyswitch(d_in, A, c->P.N, c->d_pk, c->P.pk_log2B, c->P.pk_ell, 2 * c->P.N, d_out,
+                                  (hipStream_t)stream));
+    return FDFB_OK;
+}
+
+int fdfb_pubmux(fdfb_ctx *c, const uint32_t *d_rlwe, const uint32_t *d_ctN, const int32_t *d_lut_ids,
+                uint32_t B, uint32_t *d_acc, void *stream)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    if (B == 0) return FDFB_OK;
+    if (!d_rlwe || !d_ctN || !d_lut_ids || !d_acc) return fail(FDFB_EINVAL, "null buffer");
+    int rc = ensure_device(*c);
+    if (rc) return rc;
+    K_TRY(fdfbk::launch_pubmux(c->geom, d_rlwe, d_ctN, d_lut_ids, B, c->d_luts, c->nluts, d_acc,
+                               (hipStream_t)stream));
+    return FDFB_OK;
+}
+
+int fdfb_encrypt_debug(fdfb_ctx *c, const uint32_t *m, uint32_t B, uint64_t seed, uint32_t *cts)
+{
+    if (!c || (B && (!m || !cts))) return fail(FDFB_EINVAL, "null argument");
+    const uint32_t n = c->P.n, t = 1u << c->P.log2_t, delta = 1u << (32 - c->P.log2_t);
+    const CounterRng ra(seed, kTagEncA), re(seed, kTagEncE);
+    for (uint32_t b = 0; b < B; ++b) {
+        if (m[b] >= t) return fail(FDFB_EINVAL, "message out of range [0, t)");
+        uint32_t *ct = cts + (size_t)b * (n + 1), dot = 0;
+        for (uint32_t q = 0; q < n; ++q) {
+            ct[1 + q] = ra.uniform32((uint64_t)b * n + q);
+            dot += ct[1 + q] * c->s[q];
+        }
+        ct[0] = dot + delta * m[b] + static_cast<uint32_t>(re.gaussian(b, c->P.sigma_lwe));
+    }
+    return FDFB_OK;
+}
+
+int fdfb_decrypt_debug(fdfb_ctx *c, const uint32_t *cts, uint32_t B, uint32_t dim, uint32_t *m_out,
+                       int64_t *err_out)
+{
+    if (!c || (B && (!cts || !m_out))) return fail(FDFB_EINVAL, "null argument");
+    const std::vector<uint32_t> *key = nullptr;
+    if (dim == c->P.n) key = &c->s;
+    else if (dim == c->P.N) key = &c->sf;
+    else return fail(FDFB_EINVAL, "dim must be n or N");
+    const uint32_t sh = 32 - c->P.log2_t, tmask = (1u << c->P.log2_t) - 1;
+    for (uint32_t b = 0; b < B; ++b) {
+        const uint32_t *ct = cts + (size_t)b * (dim + 1);
+        uint32_t ph = ct[0];
+        for (uint32_t q = 0; q < dim; ++q) ph -= ct[1 + q] * (*key)[q];
+        const uint32_t mm = (uint32_t)(((uint64_t)ph + (1ull << (sh - 1))) >> sh) & tmask;
+        m_out[b] = mm;
+        if (err_out) err_out[b] = (int64_t)(int32_t)(ph - (mm << sh));
+    }
+    return FDFB_OK;
+}
+
+// --- serialisation ----------------------------------------------------------
+static const char kMagic[8] = {'F', 'D', 'F', 'B', 'K', 'E', 'Y', '1'};
+
+int fdfb_export_keys(const fdfb_ctx *c, void *buf, size_t *len)
+{
+    if (!c || !len) return fail(FDFB_EINVAL, "null argument");
+    const uint64_t counts[] = {c->s.size(), c->sf.size(), c->brk.size(), c->pk.size(), c->ksk.size(),
+                               c->lut_tables.size()};
+    size_t need = sizeof(kMagic) + sizeof(fdfb_params) + 8 + 8 * 6;
+    for (uint64_t k : counts) need += 4 * k;
+    if (!buf) {
+        *len = need;
+        return FDFB_OK;
+    }
+    if (*len < need) {
+        *len = need;
+        return fail(FDFB_EINVAL, "buffer too small");
+    }
+    char *p = static_cast<char *>(buf);
+    auto put = [&](const void *src, size_t n) { std::memcpy(p, src, n); p += n; };
+    put(kMagic, 8);
+    put(&c->P, sizeof(fdfb_params));
+    put(&c->seed, 8);
+    put(counts, sizeof(counts));
+    put(c->s.data(), 4 * counts[0]);
+    put(c->sf.data(), 4 * counts[1]);
+    put(c->brk.data(), 4 * counts[2]);
+    put(c->pk.data(), 4 * counts[3]);
+    put(c->ksk.data(), 4 * counts[4]);
+    put(c->lut_tables.data(), 4 * counts[5]);
+    *len = need;
+    return FDFB_OK;
+}
+
+int fdfb_import_keys(const void *buf, size_t len, fdfb_ctx **out)
+{
+    if (!buf || !out) return fail(FDFB_EINVAL, "null argument");
+    *out = nullptr;
+    const char *p = static_cast<const char *>(buf), *end = p + len;
+    const size_t head = sizeof(kMagic) + sizeof(fdfb_params) + 8 + 8 * 6;
+    if (len < head || std::memcmp(p, kMagic, 8)) return fail(FDFB_EINVAL, "not an fdfb key blob");
+    fdfb_params P;
+    std::memcpy(&P, p + 8, sizeof(P));
+    int rc = check_params(P);
+    if (rc) return rc;
+    uint64_t seed, counts[6];
+    std::memcpy(&seed, p + 8 + sizeof(P), 8);
+    std::memcpy(counts, p + 16 + sizeof(P), sizeof(counts));
+    const uint32_t n = P.n, N = P.N, t = 1u << P.log2_t;
+    const uint64_t want[] = {n, N, (uint64_t)n * 2 * P.g_ell * 2 * N, (uint64_t)N * P.pk_ell * 2 * N,
+                             (uint64_t)N * P.ks_ell * (n + 1)};
+    for (int k = 0; k < 5; ++k)
+        if (counts[k] != want[k]) return fail(FDFB_EINVAL, "key blob sizes do not match its parameters");
+    if (counts[5] % t) return fail(FDFB_EINVAL, "malformed table section");
+    size_t need = head;
+    for (uint64_t k : counts) need += 4 * k;
+    if (len < need) return fail(FDFB_EINVAL, "truncated key blob");
+    fdfb_ctx *c = new (std::nothrow) fdfb_ctx();
+    if (!c) return fail(FDFB_ENOMEM, "context allocation failed");
+    c->P = P;
+    c->seed = seed;
+    c->geom = geometry_of(P);
+    c->mfma_ok = fdfbk::br_mfma_supported(c->geom);
+    const char *q = p + head;
+    auto take = [&](std::vector<uint32_t> &v, uint64_t k) { v.resize(k); std::memcpy(v.data(), q, 4 * k); q += 4 * k; };
+    take(c->s, counts[0]);
+    take(c->sf, counts[1]);
+    take(c->brk, counts[2]);
+    take(c->pk, counts[3]);
+    take(c->ksk, counts[4]);
+    std::vector<uint32_t> tables;
+    take(tables, counts[5]);
+    (void)end;
+    for (size_t k = 0; k < tables.size(); k += t) {
+        int32_t id;
+        rc = fdfb_register_lut(c, &tables[k], &id);
+        if (rc) { delete c; return rc; }
+    }
+    *out = c;
+    return FDFB_OK;
+}
+
+int fdfb_get_key(const fdfb_ctx *c, uint32_t which, uint32_t *host, size_t *count)
+{
+    if (!c || !count) return fail(FDFB_EINVAL, "null argument");
+    const std::vector<uint32_t> *v[] = {&c->s, &c->sf, &c->brk, &c->pk, &c->ksk};
+    if (which > 4) return fail(FDFB_EINVAL, "which must be 0..4");
+    const size_t need = v[which]->size();
+    if (!host) { *count = need; return FDFB_OK; }
+    if (*count < need) { *count = need; return fail(FDFB_EINVAL, "buffer too small"); }
+    std::memcpy(host, v[which]->data(), 4 * need);
+    *count = need;
+    return FDFB_OK;
+}
+
+void fdfb_set_abort(fdfb_ctx *c, int raised)
+{
+    if (c) c->abort_flag.store(raised ? 1 : 0);
+}
+
+void fdfb_free(fdfb_ctx *c) { delete c; }
+
+}  // extern "C"

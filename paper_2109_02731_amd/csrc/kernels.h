@@ -1,0 +1,40 @@
+// Kernel launchers of the FDFB library (host side of the HIP kernels).
+// All pointers are device pointers; every launcher enqueues on `stream`.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdfbk {
+
+struct Geometry {
+    int n, N, log2_t;
+    int g_log2B, g_ell, g_chunks;  // chunks: 7-bit pieces per gadget digit (MFMA form)
+    int ks_log2B, ks_ell;
+    int pk_log2B, pk_ell;
+    int boot_log2B, boot_ell;
+};
+
+// Number of 7-bit chunks an unsigned digit of log2B bits needs on the int8 MFMA path.
+inline int digit_chunks(int log2B) { return (log2B + 6) / 7; }
+
+// True when the batched MFMA blind rotation has an instantiation for G.
+bool br_mfma_supported(const Geometry &G);
+
+hipError_t launch_modswitch(const Geometry &G, const uint32_t *cts, uint32_t B, uint32_t *ctN,
+                            hipStream_t s);
+hipError_t launch_init_sign(const Geometry &G, const uint32_t *ctN, uint32_t B, uint32_t *acc,
+                            hipStream_t s);
+hipError_t launch_br_plain(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
+                           uint32_t accs_per_ct, const uint32_t *brk_raw, hipStream_t s);
+hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
+                          uint32_t accs_per_ct, const void *brk_frag, hipStream_t s);
+// add_base != 0: sample b of accumulator a gets add_base * L_boot^(a % per) added.
+hipError_t launch_extract(const Geometry &G, const uint32_t *acc, uint32_t A, uint32_t per,
+                          uint32_t add_base, uint32_t *lwe, hipStream_t s);
+hipError_t launch_keyswitch(const uint32_t *in, uint32_t B, uint32_t din, const uint32_t *key,
+                            int log2B, int ell, uint32_t out_len, uint32_t *out, hipStream_t s);
+hipError_t launch_pubmux(const Geometry &G, const uint32_t *rlwe, const uint32_t *ctN,
+                         const int32_t *lut_ids, uint32_t B, const int32_t *luts, int nluts,
+                         uint32_t *acc, hipStream_t s);
+
+}  // namespace fdfbk

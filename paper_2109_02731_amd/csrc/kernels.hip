@@ -1,0 +1,531 @@
+// HIP kernels of the FDFB path for gfx950 (MI355X).
+//
+// Arithmetic is exact: every ring coefficient is a uint32_t and wraps mod
+// 2^32 (q = Q = 2^32).  The blind rotation has two forms that give identical
+// bits:
+//  * k_br_mfma  -- batched: one accumulator per wavefront; each external
+//    product is a Toeplitz contraction on int8 MFMA (16x16x64) with 8-bit
+//    key limbs and int32 accumulation, recombined mod 2^32;
+//  * k_br_plain -- one accumulator per workgroup, uint32 multiply-add on the
+//    vector ALUs (the comparison form).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace fdfbk {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// ModSwitch(x, 2^32 -> 2N) = round(2N x / 2^32) mod 2N, ties up
+// (App. A Fig. "ModSwitch").
+// ---------------------------------------------------------------------------
+__global__ void k_modswitch(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                            uint32_t total, uint32_t sh, uint32_t mask)
+{
+    uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < total) out[x] = ((in[x] + (1u << (sh - 1))) >> sh) & mask;
+}
+
+// ---------------------------------------------------------------------------
+// Sign accumulators (Fig. 2 "Bootstrap", sign phase):
+// acc_{b,i} = [L_boot^i (Delta/2) sgnP X^{b_N}, 0], sgnP = 1 - X - ... - X^{N-1}.
+// ---------------------------------------------------------------------------
+__global__ void k_init_sign(const uint32_t *__restrict__ ctN, uint32_t *__restrict__ acc,
+                            uint32_t B, int n, int N, int ellb, uint32_t half, uint32_t Lb)
+{
+    const uint32_t a = blockIdx.y;  // accumulator index b * ellb + i
+    const uint32_t b = a / ellb, i = a % ellb;
+    uint32_t scale = half;
+    for (uint32_t k = 0; k < i; ++k) scale *= Lb;
+    const uint32_t e = ctN[(size_t)b * (n + 1)];
+    uint32_t *row = acc + (size_t)a * 2 * N;
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x) {
+        // coefficient m of sgnP * X^e collects sgnP[j], j = m - e (mod 2N)
+        uint32_t j = (uint32_t)(m + 2 * N - (int)e) % (2 * N);
+        int32_t v = (j < (uint32_t)N) ? (j == 0 ? 1 : -1) : (j == (uint32_t)N ? -1 : 1);
+        row[m] = scale * (uint32_t)v;
+        row[N + m] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SampleExtract(acc, 1) (App. A Fig. "SampleExtract"): b' = b_0,
+// a'_0 = a_0, a'_j = -a_{N-j}; optionally + add_base L_boot^(a mod per) on b'.
+// ---------------------------------------------------------------------------
+__global__ void k_extract(const uint32_t *__restrict__ acc, uint32_t *__restrict__ lwe, int N,
+                          uint32_t per, uint32_t add_base, uint32_t Lb)
+{
+    const uint32_t a = blockIdx.y;
+    const uint32_t *row = acc + (size_t)a * 2 * N;
+    uint32_t *o = lwe + (size_t)a * (N + 1);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j <= N; j += gridDim.x * blockDim.x) {
+        uint32_t v;
+        if (j == 0) {
+            uint32_t add = 0;
+            if (add_base) {
+                add = add_base;
+                for (uint32_t k = 0; k < a % per; ++k) add *= Lb;
+            }
+            v = row[0] + add;
+        } else if (j == 1) {
+            v = row[N];
+        } else {
+            v = 0u - row[N + (N - (j - 1))];
+        }
+        o[j] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Key switching (App. A Fig. "KeySwitch"), LWE(din) -> GLWE flattened to
+// out_len words:  out = [b, 0, ...] - sum_i sum_j Decomp(a_i)_j K[i][j].
+// Workgroup: KS_TB samples x 256 output words.  The samples' digits of one
+// chunk of input coordinates are staged in LDS; each key word is read once
+// per workgroup and used for all KS_TB samples.
+// ---------------------------------------------------------------------------
+constexpr int KS_TB = 16;
+constexpr int KS_CHUNK = 128;
+
+__global__ __launch_bounds__(256) void k_keyswitch(const uint32_t *__restrict__ in, uint32_t B,
+                                                   uint32_t din, const uint32_t *__restrict__ key,
+                                                   int log2B, int ell, uint32_t out_len,
+                                                   uint32_t *__restrict__ out)
+{
+    __shared__ uint8_t dig[KS_CHUNK * 8 * KS_TB];  // [coord][j][sample], ell <= 8
+    const uint32_t w = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t b0 = blockIdx.y * KS_TB;
+    const uint32_t drop = 32 - ell * log2B;
+    const uint32_t mask = (1u << log2B) - 1;
+    uint32_t acc[KS_TB];
+#pragma unroll
+    for (int c = 0; c < KS_TB; ++c) acc[c] = 0;
+
+    for (uint32_t i0 = 0; i0 < din; i0 += KS_CHUNK) {
+        const uint32_t cnt = min((uint32_t)KS_CHUNK, din - i0);
+        __syncthreads();
+        for (uint32_t x = threadIdx.x; x < cnt * KS_TB; x += 256) {
+            const uint32_t ii = x / KS_TB, c = x % KS_TB;
+            const uint32_t b = b0 + c;
+            uint32_t v = (b < B) ? in[(size_t)b * (din + 1) + 1 + i0 + ii] : 0u;
+            uint32_t top = drop ? (v + (1u << (drop - 1))) >> drop : v;
+            for (int j = 0; j < ell; ++j) dig[(ii * 8 + j) * KS_TB + c] = (top >> (log2B * j)) & mask;
+        }
+        __syncthreads();
+        if (w < out_len) {
+            for (uint32_t ii = 0; ii < cnt; ++ii) {
+                for (int j = 0; j < ell; ++j) {
+                    const uint32_t k = key[((size_t)(i0 + ii) * ell + j) * out_len + w];
+                    const uint8_t *dg = dig + (ii * 8 + j) * KS_TB;
+#pragma unroll
+                    for (int c = 0; c < KS_TB; ++c) acc[c] += (uint32_t)dg[c] * k;
+                }
+            }
+        }
+    }
+    if (w < out_len) {
+#pragma unroll
+        for (int c = 0; c < KS_TB; ++c) {
+            const uint32_t b = b0 + c;
+            if (b < B) {
+                uint32_t init = (w == 0) ? in[(size_t)b * (din + 1)] : 0u;
+                out[(size_t)b * out_len + w] = init - acc[c];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// PubMux of the bootstrap (Sec. 3.1 Fig. 1 with the selection of Fig. 2):
+//   p_A = rotP_1 X^{b_N}, p_B = rotP_0 X^{b_N}, delta = (p_B - p_A) mod t,
+//   acc = [Delta p_A, 0] + sum_i digit_i(delta) * R_i.
+// One workgroup per sample; digits stored as a signed negacyclic extension
+// so that every product term is a plain read.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pubmux(const uint32_t *__restrict__ rlwe,
+                                                const uint32_t *__restrict__ ctN,
+                                                const int32_t *__restrict__ lut_ids,
+                                                const int32_t *__restrict__ luts, int nluts,
+                                                uint32_t *__restrict__ acc, int n, int N,
+                                                int log2_t, int boot_log2B, int ellb)
+{
+    extern __shared__ uint8_t smem[];
+    int8_t *dx = (int8_t *)smem;                              // [ellb][2N]
+    uint32_t *pa = (uint32_t *)(smem + ((ellb * 2 * N + 15) & ~15));  // [N] Delta * p_A
+    const uint32_t b = blockIdx.x;
+    const int id = lut_ids[b];
+    uint32_t *o = acc + (size_t)b * 2 * N;
+    if (id < 0 || id >= nluts) {  // unknown table: defined, all-zero output
+        for (int m = threadIdx.x; m < 2 * N; m += blockDim.x) o[m] = 0;
+        return;
+    }
+    const int32_t *r0 = luts + (size_t)id * 2 * N, *r1 = r0 + N;
+    const uint32_t e = ctN[(size_t)b * (n + 1)];
+    const int t = 1 << log2_t;
+    const uint32_t delta = 1u << (32 - log2_t);
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        uint32_t j = (uint32_t)(m + 2 * N - (int)e) % (2 * N);
+        int32_t va = (j < (uint32_t)N) ? r1[j] : -r1[j - N];
+        int32_t vb = (j < (uint32_t)N) ? r0[j] : -r0[j - N];
+        int32_t p = (vb - va) % t;
+        if (p < 0) p += t;
+        for (int i = 0; i < ellb; ++i) {
+            int32_t d = (p >> (boot_log2B * i)) & ((1 << boot_log2B) - 1);
+            dx[i * 2 * N + N + m] = (int8_t)d;   // position m
+            dx[i * 2 * N + m] = (int8_t)(-d);    // position m - N
+        }
+        pa[m] = delta * (uint32_t)va;
+    }
+    __syncthreads();
+    const uint32_t *R = rlwe + (size_t)b * ellb * 2 * N;
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        uint32_t o0 = pa[m], o1 = 0;
+        for (int i = 0; i < ellb; ++i) {
+            const int8_t *d = dx + i * 2 * N + N + m;  // d[-p] = digit at m - p
+            const uint32_t *rb = R + (size_t)i * 2 * N, *ra = rb + N;
+            for (int p = 0; p < N; ++p) {
+                const uint32_t dv = (uint32_t)(int32_t)d[-p];
+                o0 += dv * rb[p];
+                o1 += dv * ra[p];
+            }
+        }
+        o[m] = o0;
+        o[N + m] = o1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain blind rotation (App. A Fig. "Blind Rotation"): one accumulator per
+// workgroup, schoolbook uint32 negacyclic products on the vector ALUs.
+// LDS: accumulator [2][N] u32, digits as signed extension [R][2N] int16,
+// key of the current iteration [R][2][N] u32.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_br_plain(uint32_t *__restrict__ acc_g,
+                                                  const uint32_t *__restrict__ ctN,
+                                                  uint32_t accs_per_ct, int n, int N, int log2B,
+                                                  int ell, const uint32_t *__restrict__ brk)
+{
+    extern __shared__ uint8_t smem[];
+    const int R = 2 * ell;
+    uint32_t *accL = (uint32_t *)smem;                   // [2][N]
+    uint32_t *keyL = accL + 2 * N;                       // [R][2][N]
+    int16_t *dx = (int16_t *)(keyL + (size_t)R * 2 * N);  // [R][2N]
+    const uint32_t a_idx = blockIdx.x;
+    uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
+    const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
+    const uint32_t drop = 32 - ell * log2B;
+    const uint32_t mask = (1u << log2B) - 1;
+    for (int x = threadIdx.x; x < 2 * N; x += blockDim.x) accL[x] = row[x];
+    for (int i = 0; i < n; ++i) {
+        const uint32_t a = crow[i];
+        if (a == 0) continue;  // X^0: the CMux adds extProd(C, 0) = 0
+        __syncthreads();
+        const uint32_t *kg = brk + (size_t)i * R * 2 * N;
+        for (int x = threadIdx.x; x < R * 2 * N; x += blockDim.x) keyL[x] = kg[x];
+        for (int x = threadIdx.x; x < 2 * N; x += blockDim.x) {
+            const int c = x / N, m = x % N;
+            // coefficient m of X^{-a} acc_c is acc_c[m + a] with sign flips
+            uint32_t e = (uint32_t)m + a;
+            uint32_t v = (e < (uint32_t)N) ? accL[c * N + e]
+                         : (e < 2u * N) ? 0u - accL[c * N + e - N] : accL[c * N + e - 2 * N];
+            uint32_t diff = v - accL[c * N + m];
+            uint32_t top = drop ? (diff + (1u << (drop - 1))) >> drop : diff;
+            for (int j = 0; j < ell; ++j) {
+                int16_t d = (int16_t)((top >> (log2B * j)) & mask);
+                dx[(c * ell + j) * 2 * N + N + m] = d;
+                dx[(c * ell + j) * 2 * N + m] = (int16_t)(-d);
+            }
+        }
+        __syncthreads();
+        for (int x = threadIdx.x; x < N; x += blockDim.x) {
+            uint32_t o0 = 0, o1 = 0;
+            for (int r = 0; r < R; ++r) {
+                const int16_t *d = dx + r * 2 * N + N + x;  // d[-p]: digit at x - p
+                const uint32_t *k0 = keyL + (size_t)r * 2 * N, *k1 = k0 + N;
+                for (int p = 0; p < N; ++p) {
+                    const uint32_t dv = (uint32_t)(int32_t)d[-p];
+                    o0 += dv * k0[p];
+                    o1 += dv * k1[p];
+                }
+            }
+            accL[x] += o0;
+            accL[N + x] += o1;
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < 2 * N; x += blockDim.x) row[x] = accL[x];
+}
+
+// ---------------------------------------------------------------------------
+// Batched blind rotation on int8 MFMA.
+//
+// One wavefront owns one accumulator for the whole loop over i (the CMux
+// chain is sequential in i, independent across accumulators).  For one CMux
+// the external product out_j = sum_r D_r * K_{r,j} (negacyclic) is a GEMM
+//   C[m][col] = sum_p T(D_r)[m][p] * Bk[p][col],  T(D)[m][p] = D~[m - p]
+// where D~ is the negacyclic extension of the digit polynomial (D~[x - N] =
+// -D[x]) and the 16 columns are col = s*8 + j*4 + l:
+//   s in {0,1}  key shifted by 16 (so one A tile of 16 rows yields 32 rows),
+//   j in {0,1}  output component (b, a),
+//   l in 0..3   balanced signed byte limb of the 32-bit key word.
+// The B fragments are precomputed on the host (one 1 KB lane-ordered block
+// per (i, r, k-block)); the A fragments are windows of a reversed copy of
+// D~ in wave-private LDS, aligned per lane with v_alignbyte.  A Toeplitz
+// fragment depends only on the diagonal m0 - p0, so each one is built once
+// per diagonal and used for every tile on it.  int32 accumulation is exact
+// (|sum| < R' N 127 128 < 2^31) and limbs are recombined mod 2^32 with
+// DPP quad sums.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, int ELL, int CH>
+struct BrMfma {
+    static constexpr int RPC = ELL * CH;         // virtual digit rows per component
+    static constexpr int NT = N / 32;            // output tiles of 32 rows
+    static constexpr int NKB = N / 64;           // k-blocks of 64 per row
+    static constexpr int DMAX = N - 32;          // largest diagonal m0 - p0
+    static constexpr int NDIAG = (2 * N - 96) / 32 + 1;
+    static constexpr int WAVE_WORDS = 2 * N + RPC * N / 2;  // acc u32 + digit bytes
+    static constexpr int WAVES = 4;
+};
+
+template <int N, int ELL, int CH>
+__global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g,
+                                                    const uint32_t *__restrict__ ctN,
+                                                    uint32_t accs_per_ct, uint32_t A, int n,
+                                                    const v4i *__restrict__ bfrag, int log2B)
+{
+    using G = BrMfma<N, ELL, CH>;
+    __shared__ uint32_t smem[G::WAVES * G::WAVE_WORDS];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t a_idx = blockIdx.x * G::WAVES + wv;
+    if (a_idx >= A) return;  // whole wavefront leaves together
+
+    uint32_t *accL = smem + wv * G::WAVE_WORDS;        // [2][N]
+    uint32_t *dig = accL + 2 * N;                      // RPC x (2N bytes)
+    uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
+    for (int x = lane; x < 2 * N; x += 64) accL[x] = row[x];
+    const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
+
+    const uint32_t drop = 32 - ELL * log2B;
+    const uint32_t dmask = (1u << log2B) - 1;
+    // A-fragment addressing: lane (i = lane%16, g = lane/16) reads bytes
+    // Rv[N-1-d-i+16g .. +15] of the reversed extension Rv[z] = D~[N-1-z].
+    const int ri = lane & 15, g = lane >> 4;
+    const int S0 = N - 1 - ri + 16 * g;
+    const int sh = (3 - ri) & 3;
+    const int q0 = (S0 - sh) / 4 - G::DMAX / 4;  // dword base at d = DMAX
+    // recombination: this lane's output column
+    const int limb = lane & 3, jc = (lane >> 2) & 1, ss = (lane >> 3) & 1;
+
+    wave_lds_fence();
+    for (int i = 0; i < n; ++i) {
+        const uint32_t a = __builtin_amdgcn_readfirstlane(crow[i]);
+        if (a == 0) continue;  // X^0: the CMux adds extProd(C, 0) = 0
+
+        v4i C[G::NT];
+#pragma unroll
+        for (int t = 0; t < G::NT; ++t) C[t] = v4i{0, 0, 0, 0};
+
+#pragma unroll 1
+        for (int c = 0; c < 2; ++c) {
+            // digits of (X^{-a} acc_c - acc_c), written reversed and extended
+            wave_lds_fence();
+            for (int q = lane; q < N / 4; q += 64) {
+                uint32_t pos[G::RPC], neg[G::RPC];
+#pragma unroll
+                for (int r = 0; r < G::RPC; ++r) pos[r] = neg[r] = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t m = 4 * q + u;
+                    const uint32_t e = m + a;
+                    const uint32_t v = (e < (uint32_t)N) ? accL[c * N + e]
+                                       : (e < 2u * N) ? 0u - accL[c * N + e - N]
+                                                      : accL[c * N + e - 2 * N];
+                    const uint32_t diff = v - accL[c * N + m];
+                    const uint32_t top = drop ? (diff + (1u << (drop - 1))) >> drop : diff;
+#pragma unroll
+                    for (int jj = 0; jj < ELL; ++jj) {
+                        const uint32_t dgt = (top >> (log2B * jj)) & dmask;
+#pragma unroll
+                        for (int h = 0; h < CH; ++h) {
+                            const uint32_t piece = (dgt >> (7 * h)) & 127u;
+                            pos[jj * CH + h] |= piece << (8 * (3 - u));
+                            neg[jj * CH + h] |= ((0u - piece) & 255u) << (8 * (3 - u));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < G::RPC; ++r) {
+                    uint32_t *rv = dig + r * (N / 2);
+                    rv[N / 4 - q - 1] = pos[r];
+                    rv[N / 2 - q - 1] = neg[r];
+                }
+            }
+            wave_lds_fence();
+
+#pragma unroll 1
+            for (int rr = 0; rr < G::RPC; ++rr) {
+                const int r = c * G::RPC + rr;
+                const v4i *bp = bfrag + ((size_t)(i * 2 * G::RPC + r) * G::NKB) * 64 + lane;
+                v4i Bf[G::NKB];
+#pragma unroll
+                for (int kb = 0; kb < G::NKB; ++kb) Bf[kb] = bp[kb * 64];
+                const uint32_t *ab = dig + rr * (N / 2) + q0;
+#pragma unroll
+                for (int dd = 0; dd < G::NDIAG; ++dd) {
+                    const int d = G::DMAX - 32 * dd;
+                    const uint32_t *wp = ab + 8 * dd;  // (DMAX - d) / 4
+                    const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3], w4 = wp[4];
+                    v4i Af;
+                    Af[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
+                    Af[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
+                    Af[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
+                    Af[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
+#pragma unroll
+                    for (int kb = 0; kb < G::NKB; ++kb) {
+                        const int m0 = d + 64 * kb;
+                        if (m0 >= 0 && m0 <= N - 32)
+                            C[m0 / 32] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Af, Bf[kb], C[m0 / 32],
+                                                                               0, 0, 0);
+                    }
+                }
+            }
+        }
+
+        // limbs -> uint32 (mod 2^32): sum_l C_l << 8l over the lane quad
+        wave_lds_fence();
+#pragma unroll
+        for (int t = 0; t < G::NT; ++t) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int x = (int)((uint32_t)C[t][v] << (8 * limb));
+                x += __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);  // quad xor 1
+                x += __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);  // quad xor 2
+                if (limb == 0) {
+                    const int m = 32 * t + 16 * ss + 4 * g + v;
+                    accL[jc * N + m] += (uint32_t)x;
+                }
+            }
+        }
+    }
+    wave_lds_fence();
+    for (int x = lane; x < 2 * N; x += 64) row[x] = accL[x];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int ilog2i(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
+
+hipError_t launch_modswitch(const Geometry &G, const uint32_t *cts, uint32_t B, uint32_t *ctN,
+                            hipStream_t s)
+{
+    const uint32_t total = B * (uint32_t)(G.n + 1);
+    if (!total) return hipSuccess;
+    const uint32_t sh = 32 - ilog2i(2 * G.N);
+    hipLaunchKernelGGL(k_modswitch, dim3((total + 255) / 256), dim3(256), 0, s, cts, ctN, total, sh,
+                       (uint32_t)(2 * G.N - 1));
+    return hipGetLastError();
+}
+
+hipError_t launch_init_sign(const Geometry &G, const uint32_t *ctN, uint32_t B, uint32_t *acc,
+                            hipStream_t s)
+{
+    if (!B) return hipSuccess;
+    const uint32_t half = 1u << (31 - G.log2_t);
+    hipLaunchKernelGGL(k_init_sign, dim3((G.N + 255) / 256, B * G.boot_ell), dim3(256), 0, s, ctN,
+                       acc, B, G.n, G.N, G.boot_ell, half, 1u << G.boot_log2B);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract(const Geometry &G, const uint32_t *acc, uint32_t A, uint32_t per,
+                          uint32_t add_base, uint32_t *lwe, hipStream_t s)
+{
+    if (!A) return hipSuccess;
+    hipLaunchKernelGGL(k_extract, dim3((G.N + 1 + 255) / 256, A), dim3(256), 0, s, acc, lwe, G.N, per,
+                       add_base, 1u << G.boot_log2B);
+    return hipGetLastError();
+}
+
+hipError_t launch_keyswitch(const uint32_t *in, uint32_t B, uint32_t din, const uint32_t *key,
+                            int log2B, int ell, uint32_t out_len, uint32_t *out, hipStream_t s)
+{
+    if (!B) return hipSuccess;
+    if (ell > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_keyswitch, dim3((out_len + 255) / 256, (B + KS_TB - 1) / KS_TB), dim3(256),
+                       0, s, in, B, din, key, log2B, ell, out_len, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pubmux(const Geometry &G, const uint32_t *rlwe, const uint32_t *ctN,
+                         const int32_t *lut_ids, uint32_t B, const int32_t *luts, int nluts,
+                         uint32_t *acc, hipStream_t s)
+{
+    if (!B) return hipSuccess;
+    const size_t lds = ((size_t)(G.boot_ell * 2 * G.N + 15) & ~(size_t)15) + 4 * (size_t)G.N;
+    hipLaunchKernelGGL(k_pubmux, dim3(B), dim3(256), lds, s, rlwe, ctN, lut_ids, luts, nluts, acc,
+                       G.n, G.N, G.log2_t, G.boot_log2B, G.boot_ell);
+    return hipGetLastError();
+}
+
+hipError_t launch_br_plain(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
+                           uint32_t accs_per_ct, const uint32_t *brk_raw, hipStream_t s)
+{
+    if (!A) return hipSuccess;
+    const int R = 2 * G.g_ell;
+    const size_t lds = 4 * (size_t)2 * G.N + 4 * (size_t)R * 2 * G.N + 2 * (size_t)R * 2 * G.N;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute((const void *)k_br_plain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_br_plain, dim3(A), dim3(256), lds, s, acc, ctN, accs_per_ct, G.n, G.N,
+                       G.g_log2B, G.g_ell, brk_raw);
+    return hipGetLastError();
+}
+
+template <int N, int ELL, int CH>
+static hipError_t launch_br_mfma_t(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
+                                   uint32_t accs_per_ct, const void *brk_frag, hipStream_t s)
+{
+    using GM = BrMfma<N, ELL, CH>;
+    const uint32_t blocks = (A + GM::WAVES - 1) / GM::WAVES;
+    hipLaunchKernelGGL((k_br_mfma<N, ELL, CH>), dim3(blocks), dim3(64 * GM::WAVES), 0, s, acc, ctN,
+                       accs_per_ct, A, G.n, (const v4i *)brk_frag, G.g_log2B);
+    return hipGetLastError();
+}
+
+bool br_mfma_supported(const Geometry &G)
+{
+    const int ch = digit_chunks(G.g_log2B);
+    return (G.N == 256 && G.g_ell == 2 && ch == 2) || (G.N == 1024 && G.g_ell == 3 && ch == 1) ||
+           (G.N == 256 && G.g_ell == 4 && ch == 2) || (G.N == 1024 && G.g_ell == 4 && ch == 2);
+}
+
+hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
+                          uint32_t accs_per_ct, const void *brk_frag, hipStream_t s)
+{
+    if (!A) return hipSuccess;
+    const int ch = digit_chunks(G.g_log2B);
+    if (G.N == 256 && G.g_ell == 2 && ch == 2)
+        return launch_br_mfma_t<256, 2, 2>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
+    if (G.N == 256 && G.g_ell == 4 && ch == 2)
+        return launch_br_mfma_t<256, 4, 2>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
+    if (G.N == 1024 && G.g_ell == 3 && ch == 1)
+        return launch_br_mfma_t<1024, 3, 1>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
+    if (G.N == 1024 && G.g_ell == 4 && ch == 2)
+        return launch_br_mfma_t<1024, 4, 2>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fdfbk

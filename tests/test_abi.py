@@ -1,0 +1,106 @@
+"""CPU checks of the C-ABI library: symbols, host-side key generation against
+the oracle's (same seed, independent implementations), debug encryption,
+argument validation and serialisation.  Nothing here touches a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2109_02731_amd as fd
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fdfb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdfb_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 15
+    L = fd.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(fd.EXPORTED) == names
+
+
+@pytest.mark.parametrize("preset", ["C1", "C2"])
+def test_keys_equal_oracle_keys(preset, request):
+    p = W.PRESETS[preset]
+    seed = W.KEY_SEED[preset]
+    ok = request.getfixturevalue("oracle_keys_c1" if preset == "C1" else "oracle_keys_c2")
+    ctx = fd.Context.keygen(p, seed)
+    for which, ref in enumerate([ok.s, ok.sf, ok.brk, ok.pk, ok.ksk]):
+        got = ctx.get_key(which)
+        assert np.array_equal(got, ref.reshape(-1)), which
+
+
+def test_exact_keys_equal_oracle(oracle_keys_c1_exact):
+    p = W.exact(W.C1)
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C1"])
+    for which, ref in enumerate([oracle_keys_c1_exact.brk, oracle_keys_c1_exact.pk, oracle_keys_c1_exact.ksk]):
+        assert np.array_equal(ctx.get_key(which + 2), ref.reshape(-1))
+
+
+def test_encrypt_decrypt_debug_match_oracle(oracle_keys_c1):
+    p = W.C1
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C1"])
+    msgs = W.messages(5, 40, p.t)
+    cts = ctx.encrypt_debug(msgs, seed=77)
+    ref = oracle.encrypt(p, oracle_keys_c1.s, msgs, seed=77)
+    assert np.array_equal(cts, ref)
+    m, e = ctx.decrypt_debug(cts)
+    mo, eo = oracle.decrypt(cts, oracle_keys_c1.s, p.log2_t)
+    assert np.array_equal(m, msgs) and np.array_equal(m, mo) and np.array_equal(e, eo)
+
+
+def test_rejects_bad_parameters():
+    bad = [W.C1.with_(N=300), W.C1.with_(N=8192), W.C1.with_(log2_t=9),
+           W.C1.with_(g_ell=5, g_log2B=8), W.C1.with_(boot_ell=1), W.C1.with_(ks_ell=9, ks_log2B=3),
+           W.C1.with_(sigma_glwe=-1.0)]
+    for p in bad:
+        with pytest.raises(fd.FdfbError) as ei:
+            fd.Context.keygen(p, 1)
+        assert ei.value.code == -1
+
+
+def test_lut_validation_and_ids():
+    ctx = fd.Context.keygen(W.C1, 3)
+    assert ctx.register_lut(np.arange(8)) == 0
+    assert ctx.register_lut(np.zeros(8)) == 1
+    with pytest.raises(fd.FdfbError):
+        ctx.register_lut(np.full(8, 8))
+
+
+def test_export_import_roundtrip():
+    ctx = fd.Context.keygen(W.C1, 9)
+    ctx.register_lut(W.random_lut(1, 8))
+    blob = ctx.export_keys()
+    ctx2 = fd.Context.import_keys(blob, W.C1)
+    for which in range(5):
+        assert np.array_equal(ctx.get_key(which), ctx2.get_key(which))
+    with pytest.raises(fd.FdfbError):
+        fd.Context.import_keys(blob[:100])
+    with pytest.raises(fd.FdfbError):
+        fd.Context.import_keys(b"x" * len(blob))
+
+
+def test_abort_flag_and_empty_batch_on_host():
+    """Error paths that return before any device work."""
+    ctx = fd.Context.keygen(W.C1, 4)
+    L = fd.lib()
+    assert L.fdfb_bootstrap_batch(ctx._h, None, None, 0, None, 0, None) == 0      # B = 0 is a no-op
+    assert L.fdfb_bootstrap_batch(ctx._h, None, None, 5, None, 0, None) == -1     # null buffers
+    assert L.fdfb_bootstrap_batch(ctx._h, C.c_void_p(16), C.c_void_p(16), 1, C.c_void_p(16), 0x80, None) == -1
+    ctx.set_abort(True)
+    assert L.fdfb_bootstrap_batch(ctx._h, C.c_void_p(16), C.c_void_p(16), 1, C.c_void_p(16), 0, None) == -4
+    assert b"abort" in L.fdfb_last_error()
+    ctx.set_abort(False)
+    with pytest.raises(fd.FdfbError):
+        ctx.decrypt_debug(np.zeros((1, 5), np.uint32))  # dim is neither n nor N

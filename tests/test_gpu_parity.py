@@ -1,0 +1,270 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle, bit for bit,
+through the C ABI, for both kernel forms (batched MFMA and plain VALU)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+fd = pytest.importorskip("paper_2109_02731_amd")
+
+pytestmark = pytest.mark.gpu
+M32 = 1 << 32
+FORMS = {"batched": 0, "plain": fd.PLAIN}
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def c1(oracle_keys_c1):
+    return fd.Context.keygen(W.C1, W.KEY_SEED["C1"]), oracle_keys_c1
+
+
+@pytest.fixture(scope="module")
+def c1x(oracle_keys_c1_exact):
+    return fd.Context.keygen(W.exact(W.C1), W.KEY_SEED["C1"]), oracle_keys_c1_exact
+
+
+@pytest.fixture(scope="module")
+def c2(oracle_keys_c2):
+    return fd.Context.keygen(W.C2, W.KEY_SEED["C2"]), oracle_keys_c2
+
+
+def u32(g, *shape):
+    return g.integers(0, M32, shape, dtype=np.uint64).astype(np.uint32)
+
+
+def empty(*shape):
+    return torch.empty(shape, dtype=torch.int32, device="cuda")
+
+
+def run_oracle_many(fn, count, threads=16):
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(fn, range(count)))
+
+
+# ----------------------------------------------------------------------------
+# single procedures
+# ----------------------------------------------------------------------------
+def test_modswitch(c1):
+    ctx, _ = c1
+    p = W.C1
+    cts = u32(np.random.default_rng(1), 21, p.n + 1)
+    say("modswitch C1 B=21")
+    out = fd.to_host(ctx.modswitch(fd.to_device(cts), empty(21, p.n + 1)))
+    torch.cuda.synchronize()
+    lg = int(np.log2(2 * p.N))
+    ref = np.vectorize(lambda x: oracle.modswitch(int(x), lg), otypes=[np.uint32])(cts)
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_blind_rotate_c1(c1, form):
+    ctx, ok = c1
+    p = W.C1
+    N = p.N
+    g = np.random.default_rng(2)
+    A, per = 9, 3
+    acc = u32(g, A, 2 * N)
+    ctN = g.integers(0, 2 * N, (A // per, p.n + 1)).astype(np.uint32)
+    ctN[0, 1:6] = 0  # X^0 rotations: the CMux must leave the accumulator as is
+    say(f"blind_rotate C1 {form} A={A}")
+    d_acc = fd.to_device(acc)
+    ctx.blind_rotate(d_acc, fd.to_device(ctN), accs_per_ct=per, flags=FORMS[form])
+    torch.cuda.synchronize()
+    got = fd.to_host(d_acc)
+    for a in range(A):
+        ref = oracle.blind_rotate(p, ok.brk, ctN[a // per], acc[a])
+        assert np.array_equal(got[a], ref), a
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_blind_rotate_exact_params(c1x, form):
+    ctx, ok = c1x
+    p = W.exact(W.C1)
+    N = p.N
+    g = np.random.default_rng(3)
+    acc = u32(g, 5, 2 * N)
+    ctN = g.integers(0, 2 * N, (5, p.n + 1)).astype(np.uint32)
+    say(f"blind_rotate C1-exact {form}")
+    d_acc = fd.to_device(acc)
+    ctx.blind_rotate(d_acc, fd.to_device(ctN), 1, FORMS[form])
+    torch.cuda.synchronize()
+    got = fd.to_host(d_acc)
+    for a in range(5):
+        assert np.array_equal(got[a], oracle.blind_rotate(p, ok.brk, ctN[a], acc[a])), a
+
+
+def test_sample_extract(c1):
+    ctx, _ = c1
+    p = W.C1
+    acc = u32(np.random.default_rng(4), 7, 2 * p.N)
+    say("sample_extract C1")
+    got = fd.to_host(ctx.sample_extract(fd.to_device(acc), empty(7, p.N + 1)))
+    torch.cuda.synchronize()
+    for a in range(7):
+        assert np.array_equal(got[a], oracle.sample_extract(acc[a]))
+
+
+def test_keyswitches(c1):
+    ctx, ok = c1
+    p = W.C1
+    lwe = u32(np.random.default_rng(5), 19, p.N + 1)
+    say("keyswitch / packing keyswitch C1 B=19")
+    d = fd.to_device(lwe)
+    ks = fd.to_host(ctx.keyswitch(d, empty(19, p.n + 1)))
+    pk = fd.to_host(ctx.packing_keyswitch(d, empty(19, 2 * p.N)))
+    torch.cuda.synchronize()
+    for b in range(19):
+        assert np.array_equal(ks[b], oracle.keyswitch(lwe[b], ok.ksk, p.ks_log2B, p.ks_ell, p.n + 1))
+        assert np.array_equal(pk[b], oracle.keyswitch(lwe[b], ok.pk, p.pk_log2B, p.pk_ell, 2 * p.N))
+
+
+def test_pubmux(c1):
+    ctx, _ = c1
+    p = W.C1
+    N, eb = p.N, p.boot_ell
+    g = np.random.default_rng(6)
+    luts = [W.random_lut(10 + k, p.t) for k in range(3)]
+    ids = np.array([0, 2, 1, 1, 0, 2, 2], dtype=np.int32)
+    for lut in luts:
+        ctx.register_lut(lut)
+    B = len(ids)
+    R = u32(g, B, eb, 2 * N)
+    ctN = g.integers(0, 2 * N, (B, p.n + 1)).astype(np.uint32)
+    say("pubmux C1 B=7")
+    got = fd.to_host(ctx.pubmux(fd.to_device(R), fd.to_device(ctN),
+                                torch.from_numpy(ids).cuda(), empty(B, 2 * N)))
+    torch.cuda.synchronize()
+    for b in range(B):
+        r0, r1 = oracle.setup_polynomial(luts[ids[b]], N)
+        e = int(ctN[b, 0])
+        pa = oracle.monomial_mul(r1.view(np.uint32), e).view(np.int32).astype(np.int64)
+        pb = oracle.monomial_mul(r0.view(np.uint32), e).view(np.int32).astype(np.int64)
+        assert np.array_equal(got[b], oracle.pubmux(p, R[b], pa, pb)), b
+
+
+# ----------------------------------------------------------------------------
+# full bootstrap
+# ----------------------------------------------------------------------------
+def _bootstrap(ctx, cts, ids, flags, width):
+    d_out = empty(len(cts), width)
+    ctx.bootstrap_batch(fd.to_device(cts), torch.from_numpy(np.asarray(ids, np.int32)).cuda(), d_out,
+                        flags=flags)
+    torch.cuda.synchronize()
+    return fd.to_host(d_out)
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_fdfb_c1_vs_oracle(c1, form):
+    ctx, ok = c1
+    p = W.C1
+    luts = [W.random_lut(W.LUT_SEED["C1"], p.t), W.named_luts(p.t)["relu"]]
+    lids = [ctx.register_lut(l) for l in luts]
+    msgs = np.concatenate([np.arange(p.t), W.messages(W.MSG_SEED["C1"], 13, p.t)]).astype(np.uint32)
+    B = len(msgs)  # 21: ragged against the 4-wave workgroups
+    which = np.arange(B) % 2
+    ids = np.array([lids[w] for w in which], np.int32)
+    cts = ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C1"])
+    rots = [oracle.setup_polynomial(l, p.N) for l in luts]
+    say(f"fdfb C1 {form} B={B}")
+    out = _bootstrap(ctx, cts, ids, FORMS[form], p.n + 1)
+    ref = np.stack(run_oracle_many(lambda k: oracle.fdfb(ok, *rots[which[k]], cts[k]), B))
+    assert np.array_equal(out, ref)
+    m, _ = ctx.decrypt_debug(out)
+    want = np.array([luts[which[k]][msgs[k]] for k in range(B)])
+    assert np.array_equal(m, want)
+    say(f"fdfb C1 {form} extracted")
+    outq = _bootstrap(ctx, cts, ids, FORMS[form] | fd.OUT_EXTRACTED, p.N + 1)
+    refq = np.stack(run_oracle_many(
+        lambda k: oracle.fdfb(ok, *rots[which[k]], cts[k], flags=oracle.OUT_EXTRACTED), B))
+    assert np.array_equal(outq, refq)
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_fdfb_exact_noise_free(c1x, form):
+    ctx, ok = c1x
+    p = W.exact(W.C1)
+    lut = W.named_luts(p.t)["square"]
+    lid = ctx.register_lut(lut)
+    msgs = np.arange(p.t, dtype=np.uint32)
+    cts = ctx.encrypt_debug(msgs, seed=8)
+    say(f"fdfb C1-exact {form}")
+    out = _bootstrap(ctx, cts, [lid] * p.t, FORMS[form], p.n + 1)
+    r0, r1 = oracle.setup_polynomial(lut, p.N)
+    ref = np.stack([oracle.fdfb(ok, r0, r1, cts[k]) for k in range(p.t)])
+    assert np.array_equal(out, ref)
+    delta = M32 // p.t
+    for k in range(p.t):
+        assert oracle.phase(out[k], ok.s) == (delta * int(lut[k])) % M32
+
+
+def test_batch_invariance_and_empty(c1):
+    ctx, _ = c1
+    p = W.C1
+    lid = ctx.register_lut(W.random_lut(5, p.t))
+    msgs = W.messages(17, 9, p.t)
+    cts = ctx.encrypt_debug(msgs, seed=17)
+    say("fdfb C1 batch invariance")
+    full = _bootstrap(ctx, cts, [lid] * 9, 0, p.n + 1)
+    for k in (0, 4, 8):
+        alone = _bootstrap(ctx, cts[k:k + 1], [lid], 0, p.n + 1)
+        assert np.array_equal(alone[0], full[k])
+    ctx.bootstrap_batch(empty(0, p.n + 1), empty(0), empty(0, p.n + 1))
+    bad = _bootstrap(ctx, cts[:2], [lid, 999], 0, p.n + 1)
+    assert np.array_equal(bad[0], full[0])
+    assert not bad[1].any()  # unknown table: defined all-zero output
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_blind_rotate_c2(c2, form):
+    ctx, ok = c2
+    p = W.C2
+    N = p.N
+    g = np.random.default_rng(12)
+    A = 5
+    acc = u32(g, A, 2 * N)
+    ctN = g.integers(0, 2 * N, (A, p.n + 1)).astype(np.uint32)
+    say(f"blind_rotate C2 {form} A={A}")
+    d_acc = fd.to_device(acc)
+    ctx.blind_rotate(d_acc, fd.to_device(ctN), 1, FORMS[form])
+    torch.cuda.synchronize()
+    got = fd.to_host(d_acc)
+    refs = run_oracle_many(lambda a: oracle.blind_rotate(p, ok.brk, ctN[a], acc[a]), A)
+    for a in range(A):
+        assert np.array_equal(got[a], refs[a]), a
+
+
+def test_fdfb_c2_full_batch(c2):
+    """The headline configuration at its full size: 1024 samples, one random
+    LUT.  Sampled outputs are recomputed one by one by the oracle; every output
+    must decrypt to f(m); batched and plain forms must agree on every bit."""
+    ctx, ok = c2
+    p = W.C2
+    B = 1024
+    lut = W.random_lut(W.LUT_SEED["C2"], p.t)
+    lid = ctx.register_lut(lut)
+    msgs = W.messages(W.MSG_SEED["C2"], B, p.t)
+    cts = ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C2"])
+    say("fdfb C2 batched B=1024")
+    out = _bootstrap(ctx, cts, [lid] * B, 0, p.n + 1)
+    m, err = ctx.decrypt_debug(out)
+    assert np.array_equal(m, lut[msgs])
+    r0, r1 = oracle.setup_polynomial(lut, p.N)
+    sample = [0, 1, 511, 777, 1022, 1023]
+    refs = run_oracle_many(lambda k: oracle.fdfb(ok, r0, r1, cts[sample[k]]), len(sample))
+    for k, idx in enumerate(sample):
+        assert np.array_equal(out[idx], refs[k]), idx
+    say("fdfb C2 plain B=1024")
+    outp = _bootstrap(ctx, cts, [lid] * B, fd.PLAIN, p.n + 1)
+    assert np.array_equal(outp, out)
