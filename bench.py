@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""FDFB benchmark on one MI355X.
+
+One step = one full-domain functional bootstrap of a batch of 1024 LWE
+samples at n=630, N=1024, q=2^32 (gadget 2^7 x 3, key switch 2^4 x 5,
+t=16, one seeded random LUT): ModSwitch, 2 sign blind rotations per sample,
+SampleExtract, packing key switch, public mux, the function blind rotation,
+SampleExtract and the final key switch.  Inputs are resident in HBM before the
+timed region.  Prints one JSON line with:
+
+* value: bootstraps/s of the batched INT8-MFMA form (whole job, 1 GPU);
+* plain: the same for the one-accumulator-per-workgroup VALU form;
+* latency_ms: p50 / p99 of the per-batch latency of the batched form;
+* roofline: the blind-rotation kernel's achieved int8 tera-ops/s (algorithmic
+  schoolbook work in 8-bit limbs, divided by the kernel time measured with
+  HIP events on its stream over the timed steps) against the 5.0 POPS dense
+  int8 MFMA peak, plus its HBM traffic when counter data for the current
+  kernel source exists;
+* cpu_baseline: the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FDFB bootstraps/s on 1 MI355X, n=630 N=1024, batched vs plain; p99 latency"
+PEAK_INT8_TOPS = 5000.0   # MI355X dense int8 MFMA, tera-ops/s
+PEAK_HBM_GBS = 8000.0
+
+
+def br_ops_per_accumulator(p) -> float:
+    """Algorithmic int8 ops of one blind rotation of one accumulator: n CMux,
+    each (k+1) ell (k+1) = 4 ell negacyclic products of N^2 multiply-adds,
+    every 32-bit key word split into 4 byte limbs and every digit into
+    ceil(log2B / 7) 7-bit chunks; 2 ops per multiply-add."""
+    chunks = (p.g_log2B + 6) // 7
+    return p.n * 4 * p.g_ell * p.N * p.N * 4 * chunks * 2.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2109_02731_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(unit_count: float):
+    """HBM bytes per launch of the blind-rotation kernel from committed
+    counter data, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "br_mfma_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(p, cts, lut, threads: int, sample: int):
+    import oracle
+    import workloads as W
+    keys = oracle.keygen(p, W.KEY_SEED["C2"])
+    rot = [oracle.setup_polynomial(lut, p.N)]
+    t0 = time.perf_counter()
+    oracle.fdfb_batch(keys, rot, np.zeros(sample, int), cts[:sample], threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "bootstraps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} of the 1024 samples, one oracle bootstrap per thread "
+                      f"({dt:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.calibrate_copy}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(each bootstrap is independent given the keys; see the sharding notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2109_02731_amd as fd
+    import workloads as W
+
+    p = W.C2
+    B = 1024
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C2"])
+    lut = W.random_lut(W.LUT_SEED["C2"], p.t)
+    lid = ctx.register_lut(lut)
+    msgs = W.messages(W.MSG_SEED["C2"], B, p.t)
+    cts = ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C2"])
+    d_cts = fd.to_device(cts)
+    d_ids = torch.full((B,), lid, dtype=torch.int32, device="cuda")
+    d_out = torch.empty((B, p.n + 1), dtype=torch.int32, device="cuda")
+
+    def step(flags=0):
+        ctx.bootstrap_batch(d_cts, d_ids, d_out, flags=flags)
+
+    print(f"[bench] keys ready; warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record()
+    for k in range(K):
+        step()
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(False)
+    phases, calls = ctx.profile_read()
+    step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(K)])
+    out = fd.to_host(d_out)
+    m, _ = ctx.decrypt_debug(out)
+    correct = bool(np.array_equal(m, lut[msgs]))
+    print(f"[bench] batched: {wall / K * 1e3:.2f} ms/step, correct={correct}", file=sys.stderr, flush=True)
+
+    # plain form on the same inputs
+    plain = None
+    if args.plain_steps > 0:
+        step(fd.PLAIN)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(fd.PLAIN)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t1
+        same = bool(np.array_equal(fd.to_host(d_out), out))
+        plain = {"value": B * args.plain_steps / pw, "unit": "bootstraps/s",
+                 "ms_per_step": pw / args.plain_steps * 1e3, "steps": args.plain_steps,
+                 "bit_identical_to_batched": same}
+        print(f"[bench] plain: {pw / args.plain_steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+
+    # roofline of the blind-rotation kernel (two launches per step: sign, function)
+    units_per_step = B * p.boot_ell + B
+    br_ms = (phases["sign_br"] + phases["function_br"]) / calls
+    ops = br_ops_per_accumulator(p) * units_per_step
+    achieved = ops / (br_ms * 1e-3) / 1e12
+    traffic = load_traffic(units_per_step)
+    roofline = {"bound": "mfma", "kernel": "k_br_mfma<1024,3,1>", "achieved": achieved,
+                "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_INT8_TOPS,
+                "traffic": traffic,
+                "ops_per_launch_avg": ops / 2, "avg_launch_ms": br_ms / 2,
+                "note": "int8 tera-ops/s; launches alternate 2048 and 1024 accumulators"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        print(f"[bench] cpu baseline: oracle on {threads} threads", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(p, cts, lut, threads, threads)
+
+    res = {
+        "metric": METRIC,
+        "value": B * K / wall,
+        "unit": "bootstraps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": wall / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "FDFB batch of 1024 LWE samples, n=630 N=1024 q=2^32, gadget 2^7x3, "
+                               "key switch 2^4x5, t=16, one random LUT",
+                   "batch": B, "n": p.n, "N": p.N, "t": p.t, "blind_rotations_per_bootstrap": p.boot_ell + 1},
+        "correct": correct,
+        "plain": plain,
+        "speedup_batched_vs_plain": (B * K / wall) / plain["value"] if plain else None,
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                       "what": "per-batch latency of 1024 bootstraps"},
+        "phases_ms_per_step": {k: v / calls for k, v in phases.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

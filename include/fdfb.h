@@ -53,8 +53,8 @@ extern "C" {
  * L = 2^log2B; when ell*log2B < 32 the gadget is g_j = 2^(32-ell*log2B) L^(j-1)
  * and values are rounded (half up) to their top ell*log2B bits before the
  * unsigned digit decomposition (Sec. 2 Def. "Decomposition").
- *   n, N      LWE dimension and ring degree (N a power of two, 256..2048)
- *   log2_t    plaintext modulus t = 2^log2_t, t <= 2N
+ *   n, N      LWE dimension and ring degree (N a power of two, 64..2048)
+ *   log2_t    plaintext modulus t = 2^log2_t, 2 <= t <= N
  *   g_*       blind-rotation key gadget (L_RGSW)
  *   ks_*      key switching key LWE(s_F, N) -> LWE(s, n)
  *   pk_*      packing key LWE(s_F, N) -> RLWE(s_F)
@@ -207,6 +207,27 @@ int fdfb_import_keys(const void *buf, size_t len, fdfb_ctx **out);
  * which = 0 s [n], 1 s_F [N], 2 brK [n][2 g_ell][2][N], 3 pK [N][pk_ell][2][N],
  * 4 ksK [N][ks_ell][n+1].  *count: in = capacity (words), out = words needed. */
 int fdfb_get_key(const fdfb_ctx *ctx, uint32_t which, uint32_t *host, size_t *count);
+
+/* ---- per-phase device timing ------------------------------------------- */
+
+/* Phases of fdfb_bootstrap_batch, in order. */
+#define FDFB_PHASE_MODSWITCH_INIT 0 /* ModSwitch + sign accumulators          */
+#define FDFB_PHASE_SIGN_BR 1        /* ell_boot sign blind rotations (batched) */
+#define FDFB_PHASE_EXTRACT_BITS 2   /* SampleExtract of the sign rotations     */
+#define FDFB_PHASE_PACKING_KS 3     /* LWE -> RLWE switching (BuildAcc)        */
+#define FDFB_PHASE_PUBMUX 4         /* public mux (BuildAcc)                   */
+#define FDFB_PHASE_FUNCTION_BR 5    /* function blind rotation                 */
+#define FDFB_PHASE_OUTPUT 6         /* SampleExtract + final key switch        */
+#define FDFB_NPHASES 7
+
+/* Enable (1) or disable (0) timing: while enabled, every fdfb_bootstrap_batch
+ * call records a hipEvent at each phase boundary on its stream. */
+int fdfb_profile(fdfb_ctx *ctx, int enable);
+
+/* Wait for the recorded events, add the elapsed milliseconds of each phase
+ * over all recorded calls into ms[FDFB_NPHASES] (overwritten), store the
+ * number of calls in *calls, and forget the events. */
+int fdfb_profile_read(fdfb_ctx *ctx, double *ms, uint32_t *calls);
 
 /* Raise or clear the abort flag; while raised, device entry points return
  * FDFB_EABORTED without enqueuing work. */

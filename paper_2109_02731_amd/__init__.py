@@ -51,9 +51,11 @@ EXPORTED = [
     "fdfb_keygen_from_seed", "fdfb_register_lut", "fdfb_bootstrap_batch", "fdfb_bootstrap_multi",
     "fdfb_keyswitch", "fdfb_modswitch", "fdfb_blind_rotate", "fdfb_sample_extract",
     "fdfb_packing_keyswitch", "fdfb_pubmux", "fdfb_encrypt_debug", "fdfb_decrypt_debug",
-    "fdfb_export_keys", "fdfb_import_keys", "fdfb_get_key", "fdfb_set_abort", "fdfb_free",
-    "fdfb_last_error",
+    "fdfb_export_keys", "fdfb_import_keys", "fdfb_get_key", "fdfb_profile", "fdfb_profile_read",
+    "fdfb_set_abort", "fdfb_free", "fdfb_last_error",
 ]
+
+PHASES = ["modswitch_init", "sign_br", "extract_bits", "packing_ks", "pubmux", "function_br", "output"]
 
 _lib = None
 
@@ -82,6 +84,8 @@ def lib():
             "fdfb_export_keys": (i, [P, P, C.POINTER(sz)]),
             "fdfb_import_keys": (i, [P, sz, P]),
             "fdfb_get_key": (i, [P, u32, P, C.POINTER(sz)]),
+            "fdfb_profile": (i, [P, i]),
+            "fdfb_profile_read": (i, [P, P, P]),
             "fdfb_set_abort": (None, [P, i]),
             "fdfb_free": (None, [P]),
             "fdfb_last_error": (C.c_char_p, []),
@@ -193,6 +197,16 @@ class Context:
         e = np.empty(B, np.int64)
         _check(lib().fdfb_decrypt_debug(self._h, _np_ptr(cts), B, width - 1, _np_ptr(m), _np_ptr(e)))
         return m, e
+
+    def profile(self, enable: bool = True):
+        _check(lib().fdfb_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> tuple[dict, int]:
+        """Summed milliseconds per phase over the recorded calls, and the call count."""
+        ms = (C.c_double * len(PHASES))()
+        calls = C.c_uint32()
+        _check(lib().fdfb_profile_read(self._h, ms, C.byref(calls)))
+        return dict(zip(PHASES, list(ms))), calls.value
 
     def set_abort(self, raised: bool):
         lib().fdfb_set_abort(self._h, 1 if raised else 0)

@@ -148,7 +148,14 @@ struct fdfb_ctx {
 
     std::atomic<int> abort_flag{0};
 
-    ~fdfb_ctx() { release_device(); }
+    bool profiling = false;
+    std::vector<hipEvent_t> prof_events;  // FDFB_NPHASES + 1 per recorded call
+
+    ~fdfb_ctx()
+    {
+        for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
+        release_device();
+    }
 
     void release_device()
     {
@@ -384,18 +391,31 @@ int bootstrap_one(fdfb_ctx &c, const uint32_t *d_cts, const int32_t *d_ids, uint
     const fdfbk::Geometry &G = c.geom;
     const uint32_t eb = G.boot_ell, N = G.N;
     const uint32_t half = 1u << (31 - G.log2_t);
-    // 1. ModSwitch q -> 2N
+    hipEvent_t ev[FDFB_NPHASES + 1] = {};
+    if (c.profiling) {
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        c.prof_events.insert(c.prof_events.end(), ev, ev + FDFB_NPHASES + 1);
+    }
+    auto mark = [&](int k) { return c.profiling ? hipEventRecord(ev[k], st) : hipSuccess; };
+    K_TRY(mark(0));
+    // 1. ModSwitch q -> 2N, sign accumulators
     K_TRY(fdfbk::launch_modswitch(G, d_cts, B, c.d_ctN, st));
-    // 2. sign accumulators and their blind rotation (one batched pass)
     K_TRY(fdfbk::launch_init_sign(G, c.d_ctN, B, c.d_acc_sign, st));
+    K_TRY(mark(1));
+    // 2. the ell_boot sign blind rotations of every sample, one batched pass
     K_TRY(run_br(c, c.d_acc_sign, c.d_ctN, B * eb, eb, flags, st));
+    K_TRY(mark(2));
     // 3. bit samples: SampleExtract + L_boot^i Delta/2
     K_TRY(fdfbk::launch_extract(G, c.d_acc_sign, B * eb, eb, half, c.d_cbits, st));
+    K_TRY(mark(3));
     // 4. BuildAcc: LWE -> RLWE switching, then the public mux
     K_TRY(fdfbk::launch_keyswitch(c.d_cbits, B * eb, N, c.d_pk, G.pk_log2B, G.pk_ell, 2 * N, c.d_rbits, st));
+    K_TRY(mark(4));
     K_TRY(fdfbk::launch_pubmux(G, c.d_rbits, c.d_ctN, d_ids, B, c.d_luts, c.nluts, c.d_accf, st));
+    K_TRY(mark(5));
     // 5. function blind rotation
     K_TRY(run_br(c, c.d_accf, c.d_ctN, B, 1, flags, st));
+    K_TRY(mark(6));
     // 6. SampleExtract, then LWE(N) -> LWE(n) unless the extracted form is requested
     if (flags & FDFB_OUT_EXTRACTED) {
         K_TRY(fdfbk::launch_extract(G, c.d_accf, B, 1, 0, d_out, st));
@@ -403,6 +423,7 @@ int bootstrap_one(fdfb_ctx &c, const uint32_t *d_cts, const int32_t *d_ids, uint
         K_TRY(fdfbk::launch_extract(G, c.d_accf, B, 1, 0, c.d_cq, st));
         K_TRY(fdfbk::launch_keyswitch(c.d_cq, B, N, c.d_ksk, G.ks_log2B, G.ks_ell, G.n + 1, d_out, st));
     }
+    K_TRY(mark(7));
     return FDFB_OK;
 }
 
@@ -672,6 +693,35 @@ int fdfb_get_key(const fdfb_ctx *c, uint32_t which, uint32_t *host, size_t *coun
     std::memcpy(host, v[which]->data(), 4 * need);
     *count = need;
     return FDFB_OK;
+}
+
+int fdfb_profile(fdfb_ctx *c, int enable)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    c->profiling = enable != 0;
+    return FDFB_OK;
+}
+
+int fdfb_profile_read(fdfb_ctx *c, double *ms, uint32_t *calls)
+{
+    if (!c || !ms || !calls) return fail(FDFB_EINVAL, "null argument");
+    const size_t per = FDFB_NPHASES + 1;
+    for (int k = 0; k < FDFB_NPHASES; ++k) ms[k] = 0.0;
+    *calls = (uint32_t)(c->prof_events.size() / per);
+    int rc = FDFB_OK;
+    for (size_t base = 0; base + per <= c->prof_events.size(); base += per) {
+        hipError_t e = hipEventSynchronize(c->prof_events[base + per - 1]);
+        if (e != hipSuccess) { rc = fail(FDFB_EDEVICE, hipGetErrorString(e)); break; }
+        for (int k = 0; k < FDFB_NPHASES; ++k) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, c->prof_events[base + k], c->prof_events[base + k + 1]);
+            if (e != hipSuccess) { rc = fail(FDFB_EDEVICE, hipGetErrorString(e)); break; }
+            ms[k] += t;
+        }
+    }
+    for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
+    c->prof_events.clear();
+    return rc;
 }
 
 void fdfb_set_abort(fdfb_ctx *c, int raised)
