@@ -284,33 +284,35 @@ void setup_polynomial(const uint32_t *f, uint32_t t, uint32_t N, int32_t *p0, in
         }
 }
 
-// Lane-ordered B fragments of the MFMA blind rotation: block (i, r', kb) holds,
-// for lane L and byte t, limb l of K'~[64 kb + 16 g + t + 16 s] where
-// (s, j, l) = (L/8 % 2, L/4 % 2, L % 4) of column L % 16, g = L / 16, K' the
-// key polynomial of virtual row r' (component j) times 2^(7h) for digit chunk
-// h, and K'~ its negacyclic extension.
+// Lane-ordered B fragments of the MFMA blind rotation: block (i, r', kb, j)
+// holds, for lane L and byte t, limb l of K'~[64 kb + 16 g + t + 16 s] where
+// (s, l) = (L/4 % 4, L % 4) of column L % 16, g = L / 16, K' the key polynomial
+// of virtual row r' for output component j, times 2^(7h) for digit chunk h,
+// and K'~ its negacyclic extension.
 std::vector<int8_t> build_brk_fragments(const fdfb_ctx &c)
 {
     const fdfb_params &P = c.P;
     const uint32_t N = P.N, ell = P.g_ell, CH = fdfbk::digit_chunks(P.g_log2B);
     const uint32_t RPC = ell * CH, RV = 2 * RPC, NKB = N / 64, R = 2 * ell;
-    std::vector<int8_t> out((size_t)P.n * RV * NKB * 1024);
+    std::vector<int8_t> out((size_t)P.n * RV * NKB * 2 * 1024);
     parallel_for((size_t)P.n * RV, [&](size_t id) {
         const uint32_t i = id / RV, rv = id % RV;
         const uint32_t comp_in = rv / RPC, rr = rv % RPC, jd = rr / CH, h = rr % CH;
         const uint32_t row = comp_in * ell + jd;
         for (uint32_t kb = 0; kb < NKB; ++kb)
-            for (uint32_t L = 0; L < 64; ++L) {
-                const uint32_t col = L & 15, s = col >> 3, j = (col >> 2) & 1, l = col & 3, g = L >> 4;
+            for (uint32_t j = 0; j < 2; ++j) {
                 const uint32_t *K = &c.brk[(((size_t)i * R + row) * 2 + j) * N];
-                int8_t *dst = &out[((id * NKB + kb) * 64 + L) * 16];
-                for (uint32_t t = 0; t < 16; ++t) {
-                    const uint32_t x = 64 * kb + 16 * g + t + 16 * s;  // < N + 16
-                    uint32_t w = (x < N) ? K[x] : 0u - K[x - N];
-                    w <<= 7 * h;
-                    int8_t limbs[4];
-                    balanced_limbs(w, limbs);
-                    dst[t] = limbs[l];
+                for (uint32_t L = 0; L < 64; ++L) {
+                    const uint32_t col = L & 15, s = col >> 2, l = col & 3, g = L >> 4;
+                    int8_t *dst = &out[(((id * NKB + kb) * 2 + j) * 64 + L) * 16];
+                    for (uint32_t t = 0; t < 16; ++t) {
+                        const uint32_t x = 64 * kb + 16 * g + t + 16 * s;  // < N + 64
+                        uint32_t w = (x < N) ? K[x] : 0u - K[x - N];
+                        w <<= 7 * h;
+                        int8_t limbs[4];
+                        balanced_limbs(w, limbs);
+                        dst[t] = limbs[l];
+                    }
                 }
             }
     });

@@ -3,9 +3,9 @@
 // Arithmetic is exact: every ring coefficient is a uint32_t and wraps mod
 // 2^32 (q = Q = 2^32).  The blind rotation has two forms that give identical
 // bits:
-//  * k_br_mfma  -- batched: one accumulator per wavefront; each external
-//    product is a Toeplitz contraction on int8 MFMA (16x16x64) with 8-bit
-//    key limbs and int32 accumulation, recombined mod 2^32;
+//  * k_br_mfma  -- batched: one accumulator per two-wavefront workgroup;
+//    each external product is a Toeplitz contraction on int8 MFMA (16x16x64)
+//    with 8-bit key limbs and int32 accumulation, recombined mod 2^32;
 //  * k_br_plain -- one accumulator per workgroup, uint32 multiply-add on the
 //    vector ALUs (the comparison form).
 #include <hip/hip_runtime.h>
@@ -260,58 +260,53 @@ __global__ __launch_bounds__(256) void k_br_plain(uint32_t *__restrict__ acc_g,
 // ---------------------------------------------------------------------------
 // Batched blind rotation on int8 MFMA.
 //
-// One wavefront owns one accumulator for the whole loop over i (the CMux
-// chain is sequential in i, independent across accumulators).  For one CMux
-// the external product out_j = sum_r D_r * K_{r,j} (negacyclic) is a GEMM
+// One workgroup of two wavefronts owns one accumulator for the whole loop
+// over i (the CMux chain is sequential in i, independent across
+// accumulators); wavefront j produces output component j (b or a).  For one
+// CMux the external product out_j = sum_r D_r * K_{r,j} (negacyclic) is a
+// GEMM over the digit rows r:
 //   C[m][col] = sum_p T(D_r)[m][p] * Bk[p][col],  T(D)[m][p] = D~[m - p]
-// where D~ is the negacyclic extension of the digit polynomial (D~[x - N] =
-// -D[x]) and the 16 columns are col = s*8 + j*4 + l:
-//   s in {0,1}  key shifted by 16 (so one A tile of 16 rows yields 32 rows),
-//   j in {0,1}  output component (b, a),
+// where D~ is the negacyclic extension of the digit polynomial
+// (D~[x - N] = -D[x]) and the 16 columns are col = s*4 + l:
+//   s in 0..3   key shifted by 16 s, so one A tile of 16 rows yields 64 rows,
 //   l in 0..3   balanced signed byte limb of the 32-bit key word.
-// The B fragments are precomputed on the host (one 1 KB lane-ordered block
-// per (i, r, k-block)); the A fragments are windows of a reversed copy of
-// D~ in wave-private LDS, aligned per lane with v_alignbyte.  A Toeplitz
+// B fragments are precomputed on the host (one 1 KB lane-ordered block per
+// (i, r, k-block, j)) and double-buffered in registers: the next row's block
+// is in flight while the current row runs.  A fragments are windows of a
+// reversed copy of D~ in LDS, aligned per lane with v_alignbyte; a Toeplitz
 // fragment depends only on the diagonal m0 - p0, so each one is built once
-// per diagonal and used for every tile on it.  int32 accumulation is exact
-// (|sum| < R' N 127 128 < 2^31) and limbs are recombined mod 2^32 with
-// DPP quad sums.
+// per diagonal and used for every tile on it.  Each wavefront writes the
+// digits of its own component; digit sets alternate between iterations so a
+// single barrier per CMux orders writers and readers.  int32 accumulation is
+// exact (|sum| < 2 ell CH N 127 128 < 2^31) and limbs are recombined mod 2^32
+// with DPP quad sums.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_lds_fence()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <int N, int ELL, int CH>
 struct BrMfma {
-    static constexpr int RPC = ELL * CH;         // virtual digit rows per component
-    static constexpr int NT = N / 32;            // output tiles of 32 rows
-    static constexpr int NKB = N / 64;           // k-blocks of 64 per row
-    static constexpr int DMAX = N - 32;          // largest diagonal m0 - p0
-    static constexpr int NDIAG = (2 * N - 96) / 32 + 1;
-    static constexpr int WAVE_WORDS = 2 * N + RPC * N / 2;  // acc u32 + digit bytes
-    static constexpr int WAVES = 4;
+    static constexpr int RPC = ELL * CH;     // virtual digit rows per component
+    static constexpr int RV = 2 * RPC;       // virtual digit rows per CMux
+    static constexpr int NT = N / 64;        // output tiles of 64 rows
+    static constexpr int NKB = N / 64;       // k-blocks of 64 per row
+    static constexpr int DMAX = N - 64;      // largest diagonal m0 - p0
+    static constexpr int NDIAG = 2 * N / 64 - 1;
+    static constexpr int DIG_WORDS = N / 2;  // one row of 2N digit bytes
 };
 
 template <int N, int ELL, int CH>
-__global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g,
+__global__ __launch_bounds__(128, 2) void k_br_mfma(uint32_t *__restrict__ acc_g,
                                                     const uint32_t *__restrict__ ctN,
-                                                    uint32_t accs_per_ct, uint32_t A, int n,
+                                                    uint32_t accs_per_ct, int n,
                                                     const v4i *__restrict__ bfrag, int log2B)
 {
     using G = BrMfma<N, ELL, CH>;
-    __shared__ uint32_t smem[G::WAVES * G::WAVE_WORDS];
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t a_idx = blockIdx.x * G::WAVES + wv;
-    if (a_idx >= A) return;  // whole wavefront leaves together
+    __shared__ uint32_t accL[2 * N];
+    __shared__ uint32_t dig[2][G::RV][G::DIG_WORDS];
 
-    uint32_t *accL = smem + wv * G::WAVE_WORDS;        // [2][N]
-    uint32_t *dig = accL + 2 * N;                      // RPC x (2N bytes)
-    uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
-    for (int x = lane; x < 2 * N; x += 64) accL[x] = row[x];
+    const int lane = threadIdx.x & 63;
+    const int jc = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // output component
+    const uint32_t a_idx = blockIdx.x;
+    uint32_t *row = acc_g + (size_t)a_idx * 2 * N + jc * N;
+    for (int x = lane; x < N; x += 64) accL[jc * N + x] = row[x];
     const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
 
     const uint32_t drop = 32 - ELL * log2B;
@@ -322,86 +317,131 @@ __global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
     const int S0 = N - 1 - ri + 16 * g;
     const int sh = (3 - ri) & 3;
     const int q0 = (S0 - sh) / 4 - G::DMAX / 4;  // dword base at d = DMAX
-    // recombination: this lane's output column
-    const int limb = lane & 3, jc = (lane >> 2) & 1, ss = (lane >> 3) & 1;
+    // recombination: this lane's output column (shift s, limb l)
+    const int limb = lane & 3, ss = (lane >> 2) & 3;
+    // B fragment of (i, r, kb) for this wavefront's component
+    auto frag = [&](int i, int r) {
+        return bfrag + ((size_t)(i * G::RV + r) * G::NKB * 2 + jc) * 64 + lane;
+    };
+    auto next_live = [&](int i) {
+        int k = i + 1;
+        while (k < n && __builtin_amdgcn_readfirstlane(crow[k]) == 0) ++k;
+        return k;
+    };
 
-    wave_lds_fence();
-    for (int i = 0; i < n; ++i) {
+    int i = next_live(-1);
+    v4i B0[G::NKB], B1[G::NKB];
+    {
+        const v4i *bp = frag(i < n ? i : 0, 0);
+#pragma unroll
+        for (int kb = 0; kb < G::NKB; ++kb) B0[kb] = bp[kb * 128];
+    }
+    int set = 0;
+    while (i < n) {
         const uint32_t a = __builtin_amdgcn_readfirstlane(crow[i]);
-        if (a == 0) continue;  // X^0: the CMux adds extProd(C, 0) = 0
+        const int inext = next_live(i);
+
+        // digits of (X^{-a} acc_j - acc_j), written reversed and extended.
+        // Coefficient m of X^{-a} acc is acc[(m + a) mod N], negated when
+        // (m + a) mod 2N lies in [N, 2N).  Lane q handles m = 4q..4q+3: the
+        // four rotated words come from two aligned quads of acc (conflict-free
+        // 16-byte reads) and a wave-uniform shift rho = a mod 4 picks them.
+        {
+            const uint32_t rho = a & 3, qa0 = a >> 2;
+            const uint4 *acc4 = (const uint4 *)&accL[jc * N];
+#pragma unroll
+            for (int qq = 0; qq < N / 256; ++qq) {
+                const uint32_t q = lane + 64 * qq;
+                const uint32_t Qa = (q + qa0) & (N / 2 - 1), Qb = (Qa + 1) & (N / 2 - 1);
+                const uint4 A4 = acc4[Qa & (N / 4 - 1)], B4 = acc4[Qb & (N / 4 - 1)];
+                const uint4 O4 = acc4[q];
+                const uint32_t sa = (Qa & (N / 4)) ? 0xFFFFFFFFu : 0u;
+                const uint32_t sb = (Qb & (N / 4)) ? 0xFFFFFFFFu : 0u;
+                uint32_t w[8] = {(A4.x ^ sa) - sa, (A4.y ^ sa) - sa, (A4.z ^ sa) - sa, (A4.w ^ sa) - sa,
+                                 (B4.x ^ sb) - sb, (B4.y ^ sb) - sb, (B4.z ^ sb) - sb, (B4.w ^ sb) - sb};
+                uint32_t rot[4];
+                switch (rho) {  // wave-uniform
+                case 0: rot[0] = w[0]; rot[1] = w[1]; rot[2] = w[2]; rot[3] = w[3]; break;
+                case 1: rot[0] = w[1]; rot[1] = w[2]; rot[2] = w[3]; rot[3] = w[4]; break;
+                case 2: rot[0] = w[2]; rot[1] = w[3]; rot[2] = w[4]; rot[3] = w[5]; break;
+                default: rot[0] = w[3]; rot[1] = w[4]; rot[2] = w[5]; rot[3] = w[6]; break;
+                }
+                const uint32_t own[4] = {O4.x, O4.y, O4.z, O4.w};
+                uint32_t top[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t diff = rot[u] - own[u];
+                    top[u] = drop ? (diff + (1u << (drop - 1))) >> drop : diff;
+                }
+#pragma unroll
+                for (int jj = 0; jj < ELL; ++jj) {
+#pragma unroll
+                    for (int h = 0; h < CH; ++h) {
+                        const uint32_t off = log2B * jj + 7 * h;
+                        const uint32_t wdt = (7 * (h + 1) <= log2B) ? 7u : (uint32_t)log2B - 7 * h;
+                        // bytes in memory order: coefficient 4q+3 first (reversed layout)
+                        uint32_t pos = __builtin_amdgcn_ubfe(top[3], off, wdt);
+                        pos |= __builtin_amdgcn_ubfe(top[2], off, wdt) << 8;
+                        pos |= __builtin_amdgcn_ubfe(top[1], off, wdt) << 16;
+                        pos |= __builtin_amdgcn_ubfe(top[0], off, wdt) << 24;
+                        // bytewise 0 - x for x in [0, 127], no carries between bytes
+                        const uint32_t neg = (0x80808080u - pos) ^ 0x80808080u;
+                        uint32_t *rv = dig[set][jc * G::RPC + jj * CH + h];
+                        rv[N / 4 - q - 1] = pos;
+                        rv[N / 2 - q - 1] = neg;
+                    }
+                }
+            }
+        }
+        __syncthreads();
 
         v4i C[G::NT];
 #pragma unroll
         for (int t = 0; t < G::NT; ++t) C[t] = v4i{0, 0, 0, 0};
 
-#pragma unroll 1
-        for (int c = 0; c < 2; ++c) {
-            // digits of (X^{-a} acc_c - acc_c), written reversed and extended
-            wave_lds_fence();
-            for (int q = lane; q < N / 4; q += 64) {
-                uint32_t pos[G::RPC], neg[G::RPC];
+        auto one_row = [&](const int r, v4i(&Bc)[G::NKB], v4i(&Bn)[G::NKB]) {
+            // prefetch the next row (or the next live iteration's first row);
+            // the scheduling barrier keeps the loads here, a full row ahead
+            const v4i *np = (r + 1 < G::RV) ? frag(i, r + 1) : frag(inext < n ? inext : i, 0);
 #pragma unroll
-                for (int r = 0; r < G::RPC; ++r) pos[r] = neg[r] = 0;
+            for (int kb = 0; kb < G::NKB; ++kb) Bn[kb] = np[kb * 128];
+            __builtin_amdgcn_sched_barrier(0);
+            // Toeplitz fragments, one per diagonal, ping-ponged: the words of
+            // diagonal dd+1 are read and aligned while diagonal dd's MFMAs run
+            const uint32_t *ab = dig[set][r] + q0;
+            v4i Af[2];
+            uint32_t wn[5];
+            auto read_words = [&](const int dd, uint32_t(&w)[5]) {
+                const uint32_t *wp = ab + 16 * dd;  // (DMAX - d) / 4
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t m = 4 * q + u;
-                    const uint32_t e = m + a;
-                    const uint32_t v = (e < (uint32_t)N) ? accL[c * N + e]
-                                       : (e < 2u * N) ? 0u - accL[c * N + e - N]
-                                                      : accL[c * N + e - 2 * N];
-                    const uint32_t diff = v - accL[c * N + m];
-                    const uint32_t top = drop ? (diff + (1u << (drop - 1))) >> drop : diff;
+                for (int k = 0; k < 5; ++k) w[k] = wp[k];
+            };
+            auto align = [&](const uint32_t(&w)[5], v4i &A) {
 #pragma unroll
-                    for (int jj = 0; jj < ELL; ++jj) {
-                        const uint32_t dgt = (top >> (log2B * jj)) & dmask;
+                for (int k = 0; k < 4; ++k) A[k] = (int)__builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+            };
+            read_words(0, wn);
+            align(wn, Af[0]);
 #pragma unroll
-                        for (int h = 0; h < CH; ++h) {
-                            const uint32_t piece = (dgt >> (7 * h)) & 127u;
-                            pos[jj * CH + h] |= piece << (8 * (3 - u));
-                            neg[jj * CH + h] |= ((0u - piece) & 255u) << (8 * (3 - u));
-                        }
-                    }
+            for (int dd = 0; dd < G::NDIAG; ++dd) {
+                const int d = G::DMAX - 64 * dd;
+                if (dd + 1 < G::NDIAG) read_words(dd + 1, wn);
+#pragma unroll
+                for (int kb = 0; kb < G::NKB; ++kb) {
+                    const int m0 = d + 64 * kb;
+                    if (m0 >= 0 && m0 <= N - 64)
+                        C[m0 / 64] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Af[dd & 1], Bc[kb], C[m0 / 64], 0, 0, 0);
                 }
-#pragma unroll
-                for (int r = 0; r < G::RPC; ++r) {
-                    uint32_t *rv = dig + r * (N / 2);
-                    rv[N / 4 - q - 1] = pos[r];
-                    rv[N / 2 - q - 1] = neg[r];
-                }
+                if (dd + 1 < G::NDIAG) align(wn, Af[(dd + 1) & 1]);
             }
-            wave_lds_fence();
-
-#pragma unroll 1
-            for (int rr = 0; rr < G::RPC; ++rr) {
-                const int r = c * G::RPC + rr;
-                const v4i *bp = bfrag + ((size_t)(i * 2 * G::RPC + r) * G::NKB) * 64 + lane;
-                v4i Bf[G::NKB];
+        };
 #pragma unroll
-                for (int kb = 0; kb < G::NKB; ++kb) Bf[kb] = bp[kb * 64];
-                const uint32_t *ab = dig + rr * (N / 2) + q0;
-#pragma unroll
-                for (int dd = 0; dd < G::NDIAG; ++dd) {
-                    const int d = G::DMAX - 32 * dd;
-                    const uint32_t *wp = ab + 8 * dd;  // (DMAX - d) / 4
-                    const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3], w4 = wp[4];
-                    v4i Af;
-                    Af[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
-                    Af[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
-                    Af[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
-                    Af[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
-#pragma unroll
-                    for (int kb = 0; kb < G::NKB; ++kb) {
-                        const int m0 = d + 64 * kb;
-                        if (m0 >= 0 && m0 <= N - 32)
-                            C[m0 / 32] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Af, Bf[kb], C[m0 / 32],
-                                                                               0, 0, 0);
-                    }
-                }
-            }
+        for (int r = 0; r < G::RV; ++r) {
+            if (r & 1) one_row(r, B1, B0);
+            else one_row(r, B0, B1);
         }
 
         // limbs -> uint32 (mod 2^32): sum_l C_l << 8l over the lane quad
-        wave_lds_fence();
 #pragma unroll
         for (int t = 0; t < G::NT; ++t) {
 #pragma unroll
@@ -410,15 +450,18 @@ __global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
                 x += __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);  // quad xor 1
                 x += __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);  // quad xor 2
                 if (limb == 0) {
-                    const int m = 32 * t + 16 * ss + 4 * g + v;
+                    const int m = 64 * t + 16 * ss + 4 * g + v;
                     accL[jc * N + m] += (uint32_t)x;
                 }
             }
         }
+        set ^= 1;
+        i = inext;
     }
-    wave_lds_fence();
-    for (int x = lane; x < 2 * N; x += 64) row[x] = accL[x];
+    __syncthreads();
+    for (int x = lane; x < N; x += 64) row[x] = accL[jc * N + x];
 }
+
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -498,18 +541,16 @@ template <int N, int ELL, int CH>
 static hipError_t launch_br_mfma_t(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
                                    uint32_t accs_per_ct, const void *brk_frag, hipStream_t s)
 {
-    using GM = BrMfma<N, ELL, CH>;
-    const uint32_t blocks = (A + GM::WAVES - 1) / GM::WAVES;
-    hipLaunchKernelGGL((k_br_mfma<N, ELL, CH>), dim3(blocks), dim3(64 * GM::WAVES), 0, s, acc, ctN,
-                       accs_per_ct, A, G.n, (const v4i *)brk_frag, G.g_log2B);
+    hipLaunchKernelGGL((k_br_mfma<N, ELL, CH>), dim3(A), dim3(128), 0, s, acc, ctN, accs_per_ct, G.n,
+                       (const v4i *)brk_frag, G.g_log2B);
     return hipGetLastError();
 }
 
 bool br_mfma_supported(const Geometry &G)
 {
     const int ch = digit_chunks(G.g_log2B);
-    return (G.N == 256 && G.g_ell == 2 && ch == 2) || (G.N == 1024 && G.g_ell == 3 && ch == 1) ||
-           (G.N == 256 && G.g_ell == 4 && ch == 2) || (G.N == 1024 && G.g_ell == 4 && ch == 2);
+    return (G.N == 256 && G.g_ell == 2 && ch == 2) || (G.N == 256 && G.g_ell == 4 && ch == 2) ||
+           (G.N == 1024 && G.g_ell == 3 && ch == 1);
 }
 
 hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
@@ -523,8 +564,6 @@ hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN,
         return launch_br_mfma_t<256, 4, 2>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
     if (G.N == 1024 && G.g_ell == 3 && ch == 1)
         return launch_br_mfma_t<1024, 3, 1>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
-    if (G.N == 1024 && G.g_ell == 4 && ch == 2)
-        return launch_br_mfma_t<1024, 4, 2>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
     return hipErrorInvalidValue;
 }
 
