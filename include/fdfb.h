@@ -107,7 +107,8 @@ int fdfb_register_lut(fdfb_ctx *ctx, const uint32_t *table, int32_t *lut_id);
  *   d_lut_ids  device int32[B], each a registered lut_id
  *   d_out      device uint32[B][n+1] (under s), or uint32[B][N+1] (under
  *              s_F) when FDFB_OUT_EXTRACTED is set
- *   flags      FDFB_OUT_EXTRACTED | FDFB_PLAIN
+ *   flags      FDFB_OUT_EXTRACTED | FDFB_PLAIN (FDFB_ENOTSUP when the plain form
+ *              cannot hold the parameter set, e.g. N = 2048 with ell = 4)
  * Scratch memory is taken from a pool owned by the context and grown on
  * demand (hipMalloc) the first time a larger B is seen.  B = 0 is a no-op.
  * Errors: FDFB_EINVAL (null pointer with B > 0), FDFB_ENOMEM, FDFB_EDEVICE.

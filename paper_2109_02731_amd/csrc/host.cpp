@@ -177,6 +177,16 @@ namespace {
 
 bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
+fdfbk::Geometry geometry_of(const fdfb_params &P);
+
+// The plain blind rotation keeps the accumulator, the key of one CMux and the
+// digits in LDS.
+bool plain_br_fits(const fdfb_params &P)
+{
+    const size_t R = 2 * P.g_ell;
+    return 8ull * P.N + 8ull * R * P.N + 4ull * R * P.N <= 160 * 1024;
+}
+
 int check_params(const fdfb_params &P)
 {
     if (!is_pow2(P.N) || P.N < 64 || P.N > 2048) return fail(FDFB_EINVAL, "N must be a power of two in [64, 2048]");
@@ -194,9 +204,8 @@ int check_params(const fdfb_params &P)
         return fail(FDFB_EINVAL, "boot digits must cover t: boot_ell * boot_log2B >= log2_t, log2B in [1,7]");
     if (!(P.sigma_lwe >= 0) || !(P.sigma_glwe >= 0) || !(P.sigma_pk >= 0) || !(P.sigma_ks >= 0))
         return fail(FDFB_EINVAL, "noise deviations must be non-negative");
-    const uint32_t R = 2 * P.g_ell;
-    const size_t plain_lds = 8ull * P.N + 8ull * R * P.N + 4ull * R * P.N;
-    if (plain_lds > 160 * 1024) return fail(FDFB_EINVAL, "ring degree / gadget too large for the LDS");
+    if (!plain_br_fits(P) && !fdfbk::br_mfma_supported(geometry_of(P)))
+        return fail(FDFB_EINVAL, "no blind-rotation kernel for this ring degree and gadget");
     return FDFB_OK;
 }
 
@@ -377,6 +386,14 @@ hipError_t run_br(fdfb_ctx &c, uint32_t *acc, const uint32_t *ctN, uint32_t A, u
     return fdfbk::launch_br_plain(c.geom, acc, ctN, A, per, c.d_brk, st);
 }
 
+// The requested blind-rotation form must exist for the context's parameters.
+int check_form(const fdfb_ctx &c, uint32_t flags)
+{
+    if ((flags & FDFB_PLAIN) ? !plain_br_fits(c.P) : !(c.mfma_ok || plain_br_fits(c.P)))
+        return fail(FDFB_ENOTSUP, "this blind-rotation form does not support the parameter set");
+    return FDFB_OK;
+}
+
 #define K_TRY(expr)                                                                            \
     do {                                                                                       \
         hipError_t _e = (expr);                                                                \
@@ -482,6 +499,7 @@ int fdfb_bootstrap_batch(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *d_lu
     if (B == 0) return FDFB_OK;
     if (!d_cts || !d_lut_ids || !d_out) return fail(FDFB_EINVAL, "null buffer");
     if (flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+    if (int rc = check_form(*c, flags)) return rc;
     return bootstrap_one(*c, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream);
 }
 
@@ -525,6 +543,7 @@ int fdfb_blind_rotate(fdfb_ctx *c, uint32_t *d_acc, const uint32_t *d_ctN, uint3
     if (!c) return fail(FDFB_EINVAL, "null context");
     if (A == 0) return FDFB_OK;
     if (!d_acc || !d_ctN || accs_per_ct == 0) return fail(FDFB_EINVAL, "null buffer or accs_per_ct = 0");
+    if (int rc = check_form(*c, flags)) return rc;
     int rc = ensure_device(*c);
     if (rc) return rc;
     K_TRY(run_br(*c, d_acc, d_ctN, A, accs_per_ct, flags, (hipStream_t)stream));

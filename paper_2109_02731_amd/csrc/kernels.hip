@@ -3,7 +3,7 @@
 // Arithmetic is exact: every ring coefficient is a uint32_t and wraps mod
 // 2^32 (q = Q = 2^32).  The blind rotation has two forms that give identical
 // bits:
-//  * k_br_mfma  -- batched: one accumulator per two-wavefront workgroup;
+//  * k_br_mfma  -- batched: one accumulator per workgroup of 2 or 4 waves;
 //    each external product is a Toeplitz contraction on int8 MFMA (16x16x64)
 //    with 8-bit key limbs and int32 accumulation, recombined mod 2^32;
 //  * k_br_plain -- one accumulator per workgroup, uint32 multiply-add on the
@@ -260,9 +260,11 @@ __global__ __launch_bounds__(256) void k_br_plain(uint32_t *__restrict__ acc_g,
 // ---------------------------------------------------------------------------
 // Batched blind rotation on int8 MFMA.
 //
-// One workgroup of two wavefronts owns one accumulator for the whole loop
-// over i (the CMux chain is sequential in i, independent across
-// accumulators); wavefront j produces output component j (b or a).  For one
+// One workgroup owns one accumulator for the whole loop over i (the CMux
+// chain is sequential in i, independent across accumulators); its
+// wavefronts produce output component j (b or a), one wavefront per
+// component for N <= 1024 and two (each half of the output rows) for
+// N = 2048, where key fragments also stream in chunks of 16 k-blocks.  For one
 // CMux the external product out_j = sum_r D_r * K_{r,j} (negacyclic) is a
 // GEMM over the digit rows r:
 //   C[m][col] = sum_p T(D_r)[m][p] * Bk[p][col],  T(D)[m][p] = D~[m - p]
@@ -283,45 +285,55 @@ __global__ __launch_bounds__(256) void k_br_plain(uint32_t *__restrict__ acc_g,
 // ---------------------------------------------------------------------------
 template <int N, int ELL, int CH>
 struct BrMfma {
-    static constexpr int RPC = ELL * CH;     // virtual digit rows per component
-    static constexpr int RV = 2 * RPC;       // virtual digit rows per CMux
-    static constexpr int NT = N / 64;        // output tiles of 64 rows
-    static constexpr int NKB = N / 64;       // k-blocks of 64 per row
-    static constexpr int DMAX = N - 64;      // largest diagonal m0 - p0
-    static constexpr int NDIAG = 2 * N / 64 - 1;
-    static constexpr int DIG_WORDS = N / 2;  // one row of 2N digit bytes
+    static constexpr int RPC = ELL * CH;             // virtual digit rows per component
+    static constexpr int RV = 2 * RPC;               // virtual digit rows per CMux
+    static constexpr int WPC = N > 1024 ? 2 : 1;     // wavefronts per output component
+    static constexpr int WAVES = 2 * WPC;
+    static constexpr int NT = N / 64 / WPC;          // 64-row output tiles per wavefront
+    static constexpr int NKB = N / 64;               // k-blocks of 64 per digit row
+    static constexpr int KC = NKB < 16 ? NKB : 16;   // k-blocks per key chunk
+    static constexpr int NCH = NKB / KC;             // key chunks per digit row
+    static constexpr int UNITS = RV * NCH;           // (row, chunk) units per CMux
+    static constexpr int DLOC = 64 * (NT - 1);       // largest local diagonal
+    static constexpr int NDIAG = NT + KC - 1;        // local diagonals per unit
+    static constexpr int DIG_WORDS = N / 2;          // one digit row: 2N bytes
+    static constexpr size_t LDS_BYTES = 4 * (2 * (size_t)N + 2 * (size_t)RV * DIG_WORDS);
 };
 
 template <int N, int ELL, int CH>
-__global__ __launch_bounds__(128, 2) void k_br_mfma(uint32_t *__restrict__ acc_g,
+__global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g,
                                                     const uint32_t *__restrict__ ctN,
                                                     uint32_t accs_per_ct, int n,
                                                     const v4i *__restrict__ bfrag, int log2B)
 {
     using G = BrMfma<N, ELL, CH>;
-    __shared__ uint32_t accL[2 * N];
-    __shared__ uint32_t dig[2][G::RV][G::DIG_WORDS];
+    extern __shared__ uint8_t smem[];
+    uint32_t *accL = (uint32_t *)smem;                  // [2][N]
+    uint32_t *digL = accL + 2 * N;                      // [2 sets][RV][DIG_WORDS]
+    auto dig = [&](int set, int r) { return digL + (set * G::RV + r) * G::DIG_WORDS; };
 
     const int lane = threadIdx.x & 63;
-    const int jc = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // output component
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int jc = wv / G::WPC;                          // output component of this wavefront
+    const int hw = wv % G::WPC;                          // its half of the tiles / coefficients
     const uint32_t a_idx = blockIdx.x;
-    uint32_t *row = acc_g + (size_t)a_idx * 2 * N + jc * N;
-    for (int x = lane; x < N; x += 64) accL[jc * N + x] = row[x];
+    uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
+    for (int x = threadIdx.x; x < 2 * N; x += 64 * G::WAVES) accL[x] = row[x];
     const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
 
     const uint32_t drop = 32 - ELL * log2B;
-    const uint32_t dmask = (1u << log2B) - 1;
-    // A-fragment addressing: lane (i = lane%16, g = lane/16) reads bytes
-    // Rv[N-1-d-i+16g .. +15] of the reversed extension Rv[z] = D~[N-1-z].
+    // A-fragment addressing: lane (i = lane%16, g = lane/16) of the fragment on
+    // diagonal d reads bytes Rv[N-1-d-i+16g .. +15] of the reversed extension
+    // Rv[z] = D~[N-1-z]: 5 aligned words, shifted by sh = (3 - i) mod 4.
     const int ri = lane & 15, g = lane >> 4;
-    const int S0 = N - 1 - ri + 16 * g;
     const int sh = (3 - ri) & 3;
-    const int q0 = (S0 - sh) / 4 - G::DMAX / 4;  // dword base at d = DMAX
+    const int S0 = N - 1 - ri + 16 * g;
     // recombination: this lane's output column (shift s, limb l)
     const int limb = lane & 3, ss = (lane >> 2) & 3;
-    // B fragment of (i, r, kb) for this wavefront's component
-    auto frag = [&](int i, int r) {
-        return bfrag + ((size_t)(i * G::RV + r) * G::NKB * 2 + jc) * 64 + lane;
+    // B fragments of unit u = (row, chunk) for this wavefront's component
+    auto frag = [&](int i, int u) {
+        const int r = u / G::NCH, c = u % G::NCH;
+        return bfrag + ((size_t)(i * G::RV + r) * G::NKB * 2 + c * G::KC * 2 + jc) * 64 + lane;
     };
     auto next_live = [&](int i) {
         int k = i + 1;
@@ -330,13 +342,14 @@ __global__ __launch_bounds__(128, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
     };
 
     int i = next_live(-1);
-    v4i B0[G::NKB], B1[G::NKB];
+    v4i B0[G::KC], B1[G::KC];
     {
         const v4i *bp = frag(i < n ? i : 0, 0);
 #pragma unroll
-        for (int kb = 0; kb < G::NKB; ++kb) B0[kb] = bp[kb * 128];
+        for (int kb = 0; kb < G::KC; ++kb) B0[kb] = bp[kb * 128];
     }
     int set = 0;
+    __syncthreads();
     while (i < n) {
         const uint32_t a = __builtin_amdgcn_readfirstlane(crow[i]);
         const int inext = next_live(i);
@@ -350,8 +363,8 @@ __global__ __launch_bounds__(128, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
             const uint32_t rho = a & 3, qa0 = a >> 2;
             const uint4 *acc4 = (const uint4 *)&accL[jc * N];
 #pragma unroll
-            for (int qq = 0; qq < N / 256; ++qq) {
-                const uint32_t q = lane + 64 * qq;
+            for (int qq = 0; qq < N / 256 / G::WPC; ++qq) {
+                const uint32_t q = lane + 64 * (qq + hw * (N / 256 / G::WPC));
                 const uint32_t Qa = (q + qa0) & (N / 2 - 1), Qb = (Qa + 1) & (N / 2 - 1);
                 const uint4 A4 = acc4[Qa & (N / 4 - 1)], B4 = acc4[Qb & (N / 4 - 1)];
                 const uint4 O4 = acc4[q];
@@ -386,7 +399,7 @@ __global__ __launch_bounds__(128, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
                         pos |= __builtin_amdgcn_ubfe(top[0], off, wdt) << 24;
                         // bytewise 0 - x for x in [0, 127], no carries between bytes
                         const uint32_t neg = (0x80808080u - pos) ^ 0x80808080u;
-                        uint32_t *rv = dig[set][jc * G::RPC + jj * CH + h];
+                        uint32_t *rv = dig(set, jc * G::RPC + jj * CH + h);
                         rv[N / 4 - q - 1] = pos;
                         rv[N / 2 - q - 1] = neg;
                     }
@@ -399,20 +412,23 @@ __global__ __launch_bounds__(128, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
 #pragma unroll
         for (int t = 0; t < G::NT; ++t) C[t] = v4i{0, 0, 0, 0};
 
-        auto one_row = [&](const int r, v4i(&Bc)[G::NKB], v4i(&Bn)[G::NKB]) {
-            // prefetch the next row (or the next live iteration's first row);
-            // the scheduling barrier keeps the loads here, a full row ahead
-            const v4i *np = (r + 1 < G::RV) ? frag(i, r + 1) : frag(inext < n ? inext : i, 0);
+        auto one_unit = [&](const int u, v4i(&Bc)[G::KC], v4i(&Bn)[G::KC]) {
+            // prefetch the next unit (or the next live iteration's first unit);
+            // the scheduling barrier keeps the loads here, a full unit ahead
+            const v4i *np = (u + 1 < G::UNITS) ? frag(i, u + 1) : frag(inext < n ? inext : i, 0);
 #pragma unroll
-            for (int kb = 0; kb < G::NKB; ++kb) Bn[kb] = np[kb * 128];
+            for (int kb = 0; kb < G::KC; ++kb) Bn[kb] = np[kb * 128];
             __builtin_amdgcn_sched_barrier(0);
             // Toeplitz fragments, one per diagonal, ping-ponged: the words of
-            // diagonal dd+1 are read and aligned while diagonal dd's MFMAs run
-            const uint32_t *ab = dig[set][r] + q0;
+            // diagonal dd+1 are read and aligned while diagonal dd's MFMAs run.
+            // Local diagonal dl = 64 (alpha' - kb') maps to d = dl + 64 (hw NT - c KC).
+            const int r = u / G::NCH, c = u % G::NCH;
+            const int dshift = 64 * (hw * G::NT - c * G::KC);
+            const uint32_t *ab = dig(set, r) + (S0 - dshift - sh - G::DLOC) / 4;
             v4i Af[2];
             uint32_t wn[5];
             auto read_words = [&](const int dd, uint32_t(&w)[5]) {
-                const uint32_t *wp = ab + 16 * dd;  // (DMAX - d) / 4
+                const uint32_t *wp = ab + 16 * dd;  // (DLOC - dl) / 4
 #pragma unroll
                 for (int k = 0; k < 5; ++k) w[k] = wp[k];
             };
@@ -424,21 +440,22 @@ __global__ __launch_bounds__(128, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
             align(wn, Af[0]);
 #pragma unroll
             for (int dd = 0; dd < G::NDIAG; ++dd) {
-                const int d = G::DMAX - 64 * dd;
+                const int dl = G::DLOC - 64 * dd;
                 if (dd + 1 < G::NDIAG) read_words(dd + 1, wn);
 #pragma unroll
-                for (int kb = 0; kb < G::NKB; ++kb) {
-                    const int m0 = d + 64 * kb;
-                    if (m0 >= 0 && m0 <= N - 64)
+                for (int kb = 0; kb < G::KC; ++kb) {
+                    const int m0 = dl + 64 * kb;  // local tile row
+                    if (m0 >= 0 && m0 <= 64 * (G::NT - 1))
                         C[m0 / 64] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Af[dd & 1], Bc[kb], C[m0 / 64], 0, 0, 0);
                 }
                 if (dd + 1 < G::NDIAG) align(wn, Af[(dd + 1) & 1]);
             }
         };
-#pragma unroll
-        for (int r = 0; r < G::RV; ++r) {
-            if (r & 1) one_row(r, B1, B0);
-            else one_row(r, B0, B1);
+        // units in pairs so the two fragment register sets alternate statically
+#pragma unroll 1
+        for (int u = 0; u < G::UNITS; u += 2) {
+            one_unit(u, B0, B1);
+            one_unit(u + 1, B1, B0);
         }
 
         // limbs -> uint32 (mod 2^32): sum_l C_l << 8l over the lane quad
@@ -450,18 +467,18 @@ __global__ __launch_bounds__(128, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
                 x += __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);  // quad xor 1
                 x += __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);  // quad xor 2
                 if (limb == 0) {
-                    const int m = 64 * t + 16 * ss + 4 * g + v;
+                    const int m = 64 * (hw * G::NT + t) + 16 * ss + 4 * g + v;
                     accL[jc * N + m] += (uint32_t)x;
                 }
             }
         }
+        if (G::WPC > 1) __syncthreads();  // both halves of acc_j feed the next digits
         set ^= 1;
         i = inext;
     }
     __syncthreads();
-    for (int x = lane; x < N; x += 64) row[x] = accL[jc * N + x];
+    for (int x = threadIdx.x; x < 2 * N; x += 64 * G::WAVES) row[x] = accL[x];
 }
-
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -541,16 +558,34 @@ template <int N, int ELL, int CH>
 static hipError_t launch_br_mfma_t(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
                                    uint32_t accs_per_ct, const void *brk_frag, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_br_mfma<N, ELL, CH>), dim3(A), dim3(128), 0, s, acc, ctN, accs_per_ct, G.n,
-                       (const v4i *)brk_frag, G.g_log2B);
+    using GM = BrMfma<N, ELL, CH>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_br_mfma<N, ELL, CH>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)GM::LDS_BYTES);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_br_mfma<N, ELL, CH>), dim3(A), dim3(64 * GM::WAVES), GM::LDS_BYTES, s, acc, ctN,
+                       accs_per_ct, G.n, (const v4i *)brk_frag, G.g_log2B);
     return hipGetLastError();
 }
+
+// Instantiations of the batched blind rotation: (N, ell, digit chunks).
+#define FDFB_BR_MFMA_CASES(X) \
+    X(256, 2, 2)              \
+    X(256, 4, 2)              \
+    X(1024, 3, 1)             \
+    X(2048, 2, 2)             \
+    X(2048, 4, 1)
 
 bool br_mfma_supported(const Geometry &G)
 {
     const int ch = digit_chunks(G.g_log2B);
-    return (G.N == 256 && G.g_ell == 2 && ch == 2) || (G.N == 256 && G.g_ell == 4 && ch == 2) ||
-           (G.N == 1024 && G.g_ell == 3 && ch == 1);
+#define X(n_, l_, c_) if (G.N == n_ && G.g_ell == l_ && ch == c_) return true;
+    FDFB_BR_MFMA_CASES(X)
+#undef X
+    return false;
 }
 
 hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
@@ -558,12 +593,10 @@ hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN,
 {
     if (!A) return hipSuccess;
     const int ch = digit_chunks(G.g_log2B);
-    if (G.N == 256 && G.g_ell == 2 && ch == 2)
-        return launch_br_mfma_t<256, 2, 2>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
-    if (G.N == 256 && G.g_ell == 4 && ch == 2)
-        return launch_br_mfma_t<256, 4, 2>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
-    if (G.N == 1024 && G.g_ell == 3 && ch == 1)
-        return launch_br_mfma_t<1024, 3, 1>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
+#define X(n_, l_, c_) \
+    if (G.N == n_ && G.g_ell == l_ && ch == c_) return launch_br_mfma_t<n_, l_, c_>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
+    FDFB_BR_MFMA_CASES(X)
+#undef X
     return hipErrorInvalidValue;
 }
 

@@ -268,3 +268,57 @@ def test_fdfb_c2_full_batch(c2):
     say("fdfb C2 plain B=1024")
     outp = _bootstrap(ctx, cts, [lid] * B, fd.PLAIN, p.n + 1)
     assert np.array_equal(outp, out)
+
+
+# ----------------------------------------------------------------------------
+# ring degree 2048 (two wavefronts per output component, chunked key stream)
+# ----------------------------------------------------------------------------
+N2048 = {"C3B": W.C3B, "C4": W.C4}
+
+
+@pytest.fixture(scope="module")
+def keys_2048():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            p = N2048[name]
+            cache[name] = (fd.Context.keygen(p, W.KEY_SEED[name]), oracle.keygen(p, W.KEY_SEED[name]))
+        return cache[name]
+    return get
+
+
+@pytest.mark.parametrize("name", list(N2048))
+def test_blind_rotate_n2048(keys_2048, name):
+    ctx, ok = keys_2048(name)
+    p = N2048[name]
+    N = p.N
+    g = np.random.default_rng(31)
+    A, per = 6, 2
+    acc = u32(g, A, 2 * N)
+    ctN = g.integers(0, 2 * N, (A // per, p.n + 1)).astype(np.uint32)
+    say(f"blind_rotate {name} batched A={A}")
+    d_acc = fd.to_device(acc)
+    ctx.blind_rotate(d_acc, fd.to_device(ctN), per, 0)
+    torch.cuda.synchronize()
+    got = fd.to_host(d_acc)
+    refs = run_oracle_many(lambda a: oracle.blind_rotate(p, ok.brk, ctN[a // per], acc[a]), A)
+    for a in range(A):
+        assert np.array_equal(got[a], refs[a]), a
+
+
+def test_fdfb_n2048_vs_oracle(keys_2048):
+    ctx, ok = keys_2048("C3B")
+    p = W.C3B
+    lut = W.random_lut(W.LUT_SEED["C3B"], p.t)
+    lid = ctx.register_lut(lut)
+    msgs = np.array([0, 1, p.t // 2, p.t - 1, 7, 19, 25, 30], dtype=np.uint32)
+    cts = ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C3B"])
+    say("fdfb C3B batched B=8")
+    out = _bootstrap(ctx, cts, [lid] * len(msgs), 0, p.n + 1)
+    m, _ = ctx.decrypt_debug(out)
+    assert np.array_equal(m, lut[msgs])
+    r0, r1 = oracle.setup_polynomial(lut, p.N)
+    refs = run_oracle_many(lambda k: oracle.fdfb(ok, r0, r1, cts[k]), len(msgs))
+    for k in range(len(msgs)):
+        assert np.array_equal(out[k], refs[k]), k
