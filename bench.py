@@ -16,6 +16,9 @@ timed region.  Prints one JSON line with:
   HIP events on its stream over the timed steps) against the 5.0 POPS dense
   int8 MFMA peak, plus its HBM traffic when counter data for the current
   kernel source exists;
+* serving: a Poisson request stream (two parameter sets, request sizes
+  1..512, a random table per request) through the continuous-batching server:
+  bootstraps/s and p50 / p99 request latency, saturated and at 80% load;
 * cpu_baseline: the CPU oracle on a bounded sample of the same workload.
 """
 import argparse
@@ -78,6 +81,78 @@ def cpu_baseline(p, cts, lut, threads: int, sample: int):
                       f"({dt:.1f} s wall)"}
 
 
+def serving_run(fd, torch, W, ctxs, presets, pools, lids, count, rate, max_batch=512, nstreams=3, seed=None):
+    """Poisson request stream through the continuous-batching server.
+    Returns throughput, request latency percentiles and batching counters."""
+    import threading
+    seed = W.ARRIVAL_SEED if seed is None else seed
+    times, sizes, which = W.poisson_arrivals(seed, count, rate, max_batch=max_batch)
+    rng = np.random.default_rng(seed + 1)
+    reqs = []
+    for k in range(count):
+        c, B = int(which[k]), int(sizes[k])
+        cts_d, _ = pools[c]
+        off = int(rng.integers(0, cts_d.shape[0] - B + 1))
+        j = int(rng.integers(0, len(lids[c])))
+        reqs.append((c, off, B, j, cts_d[off:off + B],
+                     torch.full((B,), lids[c][j], dtype=torch.int32, device="cuda"),
+                     torch.empty((B, presets[c].n + 1), dtype=torch.int32, device="cuda")))
+    torch.cuda.synchronize()
+    srv = fd.Server(ctxs, max_batch=max_batch, mem_budget=1 << 30, nstreams=nstreams)
+    ids, lat = [None] * count, [None] * count
+
+    def waiter():
+        for k in range(count):
+            while ids[k] is None:
+                time.sleep(1e-4)
+            lat[k] = srv.wait(ids[k])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for k, (c, off, B, j, cts, idt, out) in enumerate(reqs):
+        dt = t0 + times[k] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        ids[k] = srv.submit(c, cts, idt, out)
+    th.join()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    # every result decrypts to its table's value
+    ok = True
+    for (c, off, B, j, cts, idt, out) in reqs[:: max(1, count // 40)]:
+        m, _ = ctxs[c].decrypt_debug(fd.to_host(out))
+        want = pools[c][1][j][off:off + B]
+        ok &= bool(np.array_equal(m, want))
+    lat_ms = np.array(lat) * 1e3
+    return {"offered_requests_per_s": rate, "requests": count, "bootstraps": int(sizes.sum()),
+            "bootstraps_per_s": float(sizes.sum() / wall), "requests_per_s": count / wall,
+            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+            "batches": st["batches"], "mean_batch": float(sizes.sum() / max(1, st["batches"])),
+            "peak_admitted_mib": st["max_in_flight_bytes"] / 2 ** 20, "correct": ok}
+
+
+def serving_bench(fd, torch, W, ctx2, count):
+    """Config-5 shaped stream: parameter sets 50/50 (n=64 N=256 t=8 and the
+    bench's n=630 N=1024 t=16), request sizes uniform in 1..512, a random
+    table per request; once at 2000 requests/s (saturating) and once at 80%
+    of the capacity that run measured."""
+    presets = [W.C1, W.C2]
+    ctx1 = fd.Context.keygen(W.C1, W.KEY_SEED["C1"])
+    ctxs = [ctx1, ctx2]
+    pools, lids = [], []
+    for k, (c, p) in enumerate(zip(ctxs, presets)):
+        tables = [W.random_lut(5000 + 100 * k + j, p.t) for j in range(16)]
+        lids.append([c.register_lut(t) for t in tables])
+        msgs = W.messages(6000 + k, 4096, p.t)
+        cts = fd.to_device(c.encrypt_debug(msgs, seed=6100 + k))
+        pools.append((cts, [t[msgs] for t in tables]))
+    sat = serving_run(fd, torch, W, ctxs, presets, pools, lids, count, 2000.0)
+    sus = serving_run(fd, torch, W, ctxs, presets, pools, lids, count, 0.8 * sat["requests_per_s"], seed=W.ARRIVAL_SEED + 7)
+    return {"saturated": sat, "sustainable": sus}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +161,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--serving-requests", type=int, default=300,
+                    help="requests per serving run (0 skips the serving measurement)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -174,6 +251,11 @@ def main():
                 "ops_per_launch_avg": ops / 2, "avg_launch_ms": br_ms / 2,
                 "note": "int8 tera-ops/s; launches alternate 2048 and 1024 accumulators"}
 
+    serving = None
+    if args.serving_requests > 0:
+        print(f"[bench] serving: {args.serving_requests} requests per run", file=sys.stderr, flush=True)
+        serving = serving_bench(fd, torch, W, ctx, args.serving_requests)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
@@ -203,6 +285,7 @@ def main():
                        "what": "per-batch latency of 1024 bootstraps"},
         "phases_ms_per_step": {k: v / calls for k, v in phases.items()},
         "roofline": roofline,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

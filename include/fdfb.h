@@ -209,6 +209,59 @@ int fdfb_import_keys(const void *buf, size_t len, fdfb_ctx **out);
  * 4 ksK [N][ks_ell][n+1].  *count: in = capacity (words), out = words needed. */
 int fdfb_get_key(const fdfb_ctx *ctx, uint32_t which, uint32_t *host, size_t *count);
 
+/* ---- serving engine ----------------------------------------------------- */
+
+/*
+ * Continuous batching of bootstrap requests (the batched form of
+ * fdfb_bootstrap_batch applied to whatever requests are waiting).  A
+ * scheduler thread keeps a FIFO of waiting requests; whenever one of the
+ * server's streams is free it forms a batch from the oldest waiting request
+ * and the later ones that share its context and flags, in arrival order (at
+ * most max_batch samples), admits it only
+ * if its device scratch fits in the memory budget next to the batches in
+ * flight (a batch is always admitted when nothing is in flight), gathers the
+ * inputs, bootstraps them and scatters the outputs.  Batches on different
+ * streams overlap on the device.  Each output is bit-identical to a
+ * standalone fdfb_bootstrap_batch of that request.
+ * While a server runs, its contexts must not be used directly, and every
+ * table must be registered before fdfb_server_create.
+ */
+typedef struct fdfb_server fdfb_server;
+
+typedef struct fdfb_serving_stats {
+    uint64_t requests_done, bootstraps_done, batches;
+    uint64_t max_in_flight_bytes; /* peak admitted scratch */
+    double seconds;               /* since creation */
+} fdfb_serving_stats;
+
+/* ctxs[nctx]: parameter sets served (requests name them by index);
+ * max_batch: largest batch (and request) in samples; mem_budget: bytes of
+ * device scratch admitted at once; nstreams: 1..8 device streams.
+ * Allocates the staging buffers and uploads keys.  Errors: FDFB_EINVAL,
+ * FDFB_ENOMEM, FDFB_EDEVICE. */
+int fdfb_server_create(fdfb_ctx *const *ctxs, uint32_t nctx, uint32_t max_batch, size_t mem_budget,
+                       uint32_t nstreams, fdfb_server **out);
+
+/* Enqueue a request of B samples (1 <= B <= max_batch) of context ctx_index:
+ * same buffers and flags as fdfb_bootstrap_batch, device memory owned by the
+ * caller and untouched until the request completes.  Thread-safe; returns
+ * at once with *req_id. */
+int fdfb_server_submit(fdfb_server *srv, uint32_t ctx_index, const uint32_t *d_cts,
+                       const int32_t *d_lut_ids, uint32_t B, uint32_t *d_out, uint32_t flags,
+                       uint64_t *req_id);
+
+/* *done = 1 once the request's outputs are in place (0 while pending). */
+int fdfb_server_poll(fdfb_server *srv, uint64_t req_id, int *done);
+
+/* Block until the request completes; latency_s (nullable) receives the time
+ * from submission to observed completion.  Forgets the request id. */
+int fdfb_server_wait(fdfb_server *srv, uint64_t req_id, double *latency_s);
+
+int fdfb_server_stats(fdfb_server *srv, fdfb_serving_stats *out);
+
+/* Finish the waiting and running requests, then release the server. */
+void fdfb_server_destroy(fdfb_server *srv);
+
 /* ---- per-phase device timing ------------------------------------------- */
 
 /* Phases of fdfb_bootstrap_batch, in order. */

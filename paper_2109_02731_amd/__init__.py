@@ -42,6 +42,11 @@ class _Params(C.Structure):
                 ("sigma_pk", C.c_double), ("sigma_ks", C.c_double)]
 
 
+class _ServerStats(C.Structure):
+    _fields_ = [("requests_done", C.c_uint64), ("bootstraps_done", C.c_uint64), ("batches", C.c_uint64),
+                ("max_in_flight_bytes", C.c_uint64), ("seconds", C.c_double)]
+
+
 class _Job(C.Structure):
     _fields_ = [("ctx", C.c_void_p), ("d_cts", C.c_void_p), ("d_lut_ids", C.c_void_p),
                 ("B", C.c_uint32), ("d_out", C.c_void_p), ("flags", C.c_uint32)]
@@ -53,6 +58,8 @@ EXPORTED = [
     "fdfb_packing_keyswitch", "fdfb_pubmux", "fdfb_encrypt_debug", "fdfb_decrypt_debug",
     "fdfb_export_keys", "fdfb_import_keys", "fdfb_get_key", "fdfb_profile", "fdfb_profile_read",
     "fdfb_set_abort", "fdfb_free", "fdfb_last_error",
+    "fdfb_server_create", "fdfb_server_submit", "fdfb_server_poll", "fdfb_server_wait",
+    "fdfb_server_stats", "fdfb_server_destroy",
 ]
 
 PHASES = ["modswitch_init", "sign_br", "extract_bits", "packing_ks", "pubmux", "function_br", "output"]
@@ -89,6 +96,12 @@ def lib():
             "fdfb_set_abort": (None, [P, i]),
             "fdfb_free": (None, [P]),
             "fdfb_last_error": (C.c_char_p, []),
+            "fdfb_server_create": (i, [P, u32, u32, sz, u32, P]),
+            "fdfb_server_submit": (i, [P, u32, P, P, u32, P, u32, P]),
+            "fdfb_server_poll": (i, [P, C.c_uint64, P]),
+            "fdfb_server_wait": (i, [P, C.c_uint64, P]),
+            "fdfb_server_stats": (i, [P, P]),
+            "fdfb_server_destroy": (None, [P]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -248,6 +261,50 @@ class Context:
                                  _dev_ptr(lut_ids, "lut_ids"), int(out.shape[0]), _dev_ptr(out, "out"),
                                  _stream(stream)))
         return out
+
+
+class Server:
+    """Continuous-batching bootstrap server over one or more contexts."""
+
+    def __init__(self, ctxs, max_batch: int = 1024, mem_budget: int = 1 << 30, nstreams: int = 2):
+        self.ctxs = list(ctxs)  # keep the contexts alive
+        arr = (C.c_void_p * len(self.ctxs))(*[c._h.value if isinstance(c._h, C.c_void_p) else c._h
+                                              for c in self.ctxs])
+        h = C.c_void_p()
+        _check(lib().fdfb_server_create(arr, len(self.ctxs), max_batch, mem_budget, nstreams, C.byref(h)))
+        self._h = h
+
+    def submit(self, ctx_index: int, cts, lut_ids, out, flags: int = 0) -> int:
+        rid = C.c_uint64()
+        _check(lib().fdfb_server_submit(self._h, ctx_index, _dev_ptr(cts, "cts"), _dev_ptr(lut_ids, "lut_ids"),
+                                        int(cts.shape[0]), _dev_ptr(out, "out"), flags, C.byref(rid)))
+        return rid.value
+
+    def poll(self, rid: int) -> bool:
+        done = C.c_int()
+        _check(lib().fdfb_server_poll(self._h, rid, C.byref(done)))
+        return bool(done.value)
+
+    def wait(self, rid: int) -> float:
+        lat = C.c_double()
+        _check(lib().fdfb_server_wait(self._h, rid, C.byref(lat)))
+        return lat.value
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().fdfb_server_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().fdfb_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def bootstrap_multi(jobs, stream=None):

@@ -13,9 +13,10 @@
 #include <vector>
 
 #include "fdfb.h"
+#include "internal.h"
 #include "kernels.h"
 
-namespace {
+namespace fdfbi {
 
 thread_local std::string g_last_error;
 
@@ -24,6 +25,13 @@ int fail(int code, const std::string &msg)
     g_last_error = msg;
     return code;
 }
+
+}  // namespace fdfbi
+
+using fdfbi::fail;
+using fdfbi::g_last_error;
+
+namespace {
 
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
@@ -121,57 +129,6 @@ inline void balanced_limbs(uint32_t w, int8_t out[4])
 }
 
 }  // namespace
-
-// ============================================================================
-// context
-// ============================================================================
-struct fdfb_ctx {
-    fdfb_params P{};
-    uint64_t seed = 0;
-    std::vector<uint32_t> s, sf, brk, pk, ksk;
-    std::vector<uint32_t> lut_tables;  // [nluts][t]
-    std::vector<int32_t> lut_polys;    // [nluts][2][N]: rotP_0, rotP_1
-    int nluts = 0;
-
-    fdfbk::Geometry geom{};
-    bool mfma_ok = false;
-
-    bool on_device = false;
-    uint32_t *d_brk = nullptr, *d_pk = nullptr, *d_ksk = nullptr;
-    void *d_brk_frag = nullptr;
-    int32_t *d_luts = nullptr;
-    int dev_nluts = 0;
-
-    uint32_t cap = 0;  // scratch capacity in samples
-    uint32_t *d_ctN = nullptr, *d_acc_sign = nullptr, *d_cbits = nullptr, *d_rbits = nullptr,
-             *d_accf = nullptr, *d_cq = nullptr;
-
-    std::atomic<int> abort_flag{0};
-
-    bool profiling = false;
-    std::vector<hipEvent_t> prof_events;  // FDFB_NPHASES + 1 per recorded call
-
-    ~fdfb_ctx()
-    {
-        for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
-        release_device();
-    }
-
-    void release_device()
-    {
-        for (void *p : {(void *)d_brk, (void *)d_pk, (void *)d_ksk, d_brk_frag, (void *)d_luts,
-                        (void *)d_ctN, (void *)d_acc_sign, (void *)d_cbits, (void *)d_rbits,
-                        (void *)d_accf, (void *)d_cq})
-            if (p) (void)hipFree(p);
-        d_brk = d_pk = d_ksk = nullptr;
-        d_brk_frag = nullptr;
-        d_luts = nullptr;
-        d_ctN = d_acc_sign = d_cbits = d_rbits = d_accf = d_cq = nullptr;
-        on_device = false;
-        dev_nluts = 0;
-        cap = 0;
-    }
-};
 
 namespace {
 
@@ -331,12 +288,19 @@ std::vector<int8_t> build_brk_fragments(const fdfb_ctx &c)
 template <class T>
 int dev_upload(T **dst, const T *src, size_t count)
 {
-    if (*dst) (void)hipFree(*dst);
+    if (*dst) {
+        (void)hipDeviceSynchronize();  // earlier launches may still read the old buffer
+        (void)hipFree(*dst);
+    }
     *dst = nullptr;
     HIP_TRY(hipMalloc((void **)dst, std::max<size_t>(count, 1) * sizeof(T)));
     if (count) HIP_TRY(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
     return FDFB_OK;
 }
+
+}  // namespace
+
+namespace fdfbi {
 
 int ensure_device(fdfb_ctx &c)
 {
@@ -362,21 +326,43 @@ int ensure_device(fdfb_ctx &c)
     return FDFB_OK;
 }
 
-int ensure_scratch(fdfb_ctx &c, uint32_t B)
+
+size_t Scratch::bytes_for(const fdfb_params &P, uint32_t B)
 {
-    if (B <= c.cap) return FDFB_OK;
+    const size_t n1 = P.n + 1, N = P.N, eb = P.boot_ell;
+    return 4 * (B * n1 + B * eb * 2 * N + B * eb * (N + 1) + B * eb * 2 * N + B * 2 * N + B * (N + 1));
+}
+
+void Scratch::release()
+{
+    for (uint32_t *p : {ctN, acc_sign, cbits, rbits, accf, cq})
+        if (p) (void)hipFree(p);
+    ctN = acc_sign = cbits = rbits = accf = cq = nullptr;
+    cap = 0;
+}
+
+int ensure_scratch(fdfb_ctx &c, Scratch &sc, uint32_t B)
+{
+    if (B <= sc.cap) return FDFB_OK;
+    sc.release();
     const size_t n1 = c.P.n + 1, N = c.P.N, eb = c.P.boot_ell;
-    uint32_t **bufs[] = {&c.d_ctN, &c.d_acc_sign, &c.d_cbits, &c.d_rbits, &c.d_accf, &c.d_cq};
+    uint32_t **bufs[] = {&sc.ctN, &sc.acc_sign, &sc.cbits, &sc.rbits, &sc.accf, &sc.cq};
     const size_t words[] = {B * n1, B * eb * 2 * N, B * eb * (N + 1), B * eb * 2 * N, B * 2 * N, B * (N + 1)};
     for (int k = 0; k < 6; ++k) {
-        if (*bufs[k]) (void)hipFree(*bufs[k]);
-        *bufs[k] = nullptr;
+        hipError_t e = hipMalloc((void **)bufs[k], words[k] * 4);
+        if (e != hipSuccess) {
+            sc.release();
+            return fail(e == hipErrorOutOfMemory ? FDFB_ENOMEM : FDFB_EDEVICE,
+                        std::string("scratch allocation: ") + hipGetErrorString(e));
+        }
     }
-    c.cap = 0;
-    for (int k = 0; k < 6; ++k) HIP_TRY(hipMalloc((void **)bufs[k], words[k] * 4));
-    c.cap = B;
+    sc.cap = B;
     return FDFB_OK;
 }
+
+}  // namespace fdfbi
+
+namespace fdfbi {
 
 hipError_t run_br(fdfb_ctx &c, uint32_t *acc, const uint32_t *ctN, uint32_t A, uint32_t per,
                   uint32_t flags, hipStream_t st)
@@ -401,12 +387,12 @@ int check_form(const fdfb_ctx &c, uint32_t flags)
             return fail(FDFB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));      \
     } while (0)
 
-int bootstrap_one(fdfb_ctx &c, const uint32_t *d_cts, const int32_t *d_ids, uint32_t B, uint32_t *d_out,
-                  uint32_t flags, hipStream_t st)
+int bootstrap_with(fdfb_ctx &c, Scratch &sc, const uint32_t *d_cts, const int32_t *d_ids, uint32_t B,
+                   uint32_t *d_out, uint32_t flags, hipStream_t st)
 {
     int rc;
     if ((rc = ensure_device(c))) return rc;
-    if ((rc = ensure_scratch(c, B))) return rc;
+    if ((rc = ensure_scratch(c, sc, B))) return rc;
     const fdfbk::Geometry &G = c.geom;
     const uint32_t eb = G.boot_ell, N = G.N;
     const uint32_t half = 1u << (31 - G.log2_t);
@@ -418,35 +404,37 @@ int bootstrap_one(fdfb_ctx &c, const uint32_t *d_cts, const int32_t *d_ids, uint
     auto mark = [&](int k) { return c.profiling ? hipEventRecord(ev[k], st) : hipSuccess; };
     K_TRY(mark(0));
     // 1. ModSwitch q -> 2N, sign accumulators
-    K_TRY(fdfbk::launch_modswitch(G, d_cts, B, c.d_ctN, st));
-    K_TRY(fdfbk::launch_init_sign(G, c.d_ctN, B, c.d_acc_sign, st));
+    K_TRY(fdfbk::launch_modswitch(G, d_cts, B, sc.ctN, st));
+    K_TRY(fdfbk::launch_init_sign(G, sc.ctN, B, sc.acc_sign, st));
     K_TRY(mark(1));
     // 2. the ell_boot sign blind rotations of every sample, one batched pass
-    K_TRY(run_br(c, c.d_acc_sign, c.d_ctN, B * eb, eb, flags, st));
+    K_TRY(run_br(c, sc.acc_sign, sc.ctN, B * eb, eb, flags, st));
     K_TRY(mark(2));
     // 3. bit samples: SampleExtract + L_boot^i Delta/2
-    K_TRY(fdfbk::launch_extract(G, c.d_acc_sign, B * eb, eb, half, c.d_cbits, st));
+    K_TRY(fdfbk::launch_extract(G, sc.acc_sign, B * eb, eb, half, sc.cbits, st));
     K_TRY(mark(3));
     // 4. BuildAcc: LWE -> RLWE switching, then the public mux
-    K_TRY(fdfbk::launch_keyswitch(c.d_cbits, B * eb, N, c.d_pk, G.pk_log2B, G.pk_ell, 2 * N, c.d_rbits, st));
+    K_TRY(fdfbk::launch_keyswitch(sc.cbits, B * eb, N, c.d_pk, G.pk_log2B, G.pk_ell, 2 * N, sc.rbits, st));
     K_TRY(mark(4));
-    K_TRY(fdfbk::launch_pubmux(G, c.d_rbits, c.d_ctN, d_ids, B, c.d_luts, c.nluts, c.d_accf, st));
+    K_TRY(fdfbk::launch_pubmux(G, sc.rbits, sc.ctN, d_ids, B, c.d_luts, c.nluts, sc.accf, st));
     K_TRY(mark(5));
     // 5. function blind rotation
-    K_TRY(run_br(c, c.d_accf, c.d_ctN, B, 1, flags, st));
+    K_TRY(run_br(c, sc.accf, sc.ctN, B, 1, flags, st));
     K_TRY(mark(6));
     // 6. SampleExtract, then LWE(N) -> LWE(n) unless the extracted form is requested
     if (flags & FDFB_OUT_EXTRACTED) {
-        K_TRY(fdfbk::launch_extract(G, c.d_accf, B, 1, 0, d_out, st));
+        K_TRY(fdfbk::launch_extract(G, sc.accf, B, 1, 0, d_out, st));
     } else {
-        K_TRY(fdfbk::launch_extract(G, c.d_accf, B, 1, 0, c.d_cq, st));
-        K_TRY(fdfbk::launch_keyswitch(c.d_cq, B, N, c.d_ksk, G.ks_log2B, G.ks_ell, G.n + 1, d_out, st));
+        K_TRY(fdfbk::launch_extract(G, sc.accf, B, 1, 0, sc.cq, st));
+        K_TRY(fdfbk::launch_keyswitch(sc.cq, B, N, c.d_ksk, G.ks_log2B, G.ks_ell, G.n + 1, d_out, st));
     }
     K_TRY(mark(7));
     return FDFB_OK;
 }
 
-}  // namespace
+}  // namespace fdfbi
+
+using namespace fdfbi;
 
 // ============================================================================
 // C ABI
@@ -500,7 +488,7 @@ int fdfb_bootstrap_batch(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *d_lu
     if (!d_cts || !d_lut_ids || !d_out) return fail(FDFB_EINVAL, "null buffer");
     if (flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
     if (int rc = check_form(*c, flags)) return rc;
-    return bootstrap_one(*c, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream);
+    return bootstrap_with(*c, c->scratch, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream);
 }
 
 int fdfb_bootstrap_multi(const fdfb_job *jobs, uint32_t njobs, void *stream)

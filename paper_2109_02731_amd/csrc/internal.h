@@ -1,0 +1,73 @@
+// Internal interfaces of the FDFB host core shared by the C ABI (host.cpp)
+// and the serving engine (server.cpp).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <string>
+#include <vector>
+
+#include "fdfb.h"
+#include "kernels.h"
+
+namespace fdfbi {
+
+// Device scratch of one bootstrap batch: ModSwitched samples, sign
+// accumulators, bit samples, switched RLWE samples, built accumulators, c_Q.
+struct Scratch {
+    uint32_t cap = 0;  // capacity in samples
+    uint32_t *ctN = nullptr, *acc_sign = nullptr, *cbits = nullptr, *rbits = nullptr, *accf = nullptr,
+             *cq = nullptr;
+    static size_t bytes_for(const fdfb_params &P, uint32_t B);
+    void release();
+    ~Scratch() { release(); }
+};
+
+}  // namespace fdfbi
+
+struct fdfb_ctx {
+    fdfb_params P{};
+    uint64_t seed = 0;
+    std::vector<uint32_t> s, sf, brk, pk, ksk;
+    std::vector<uint32_t> lut_tables;  // [nluts][t]
+    std::vector<int32_t> lut_polys;    // [nluts][2][N]: rotP_0, rotP_1
+    int nluts = 0;
+
+    fdfbk::Geometry geom{};
+    bool mfma_ok = false;
+
+    bool on_device = false;
+    uint32_t *d_brk = nullptr, *d_pk = nullptr, *d_ksk = nullptr;
+    void *d_brk_frag = nullptr;
+    int32_t *d_luts = nullptr;
+    int dev_nluts = 0;
+
+    fdfbi::Scratch scratch;  // for direct (non-server) calls
+
+    std::atomic<int> abort_flag{0};
+
+    bool profiling = false;
+    std::vector<hipEvent_t> prof_events;  // FDFB_NPHASES + 1 per recorded call
+
+    ~fdfb_ctx()
+    {
+        for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
+        scratch.release();
+        for (void *p : {(void *)d_brk, (void *)d_pk, (void *)d_ksk, d_brk_frag, (void *)d_luts})
+            if (p) (void)hipFree(p);
+    }
+};
+
+namespace fdfbi {
+
+int fail(int code, const std::string &msg);
+// Upload keys and registered tables on first use (or after new tables).
+int ensure_device(fdfb_ctx &c);
+int ensure_scratch(fdfb_ctx &c, Scratch &sc, uint32_t B);
+// The requested blind-rotation form must exist for the context's parameters.
+int check_form(const fdfb_ctx &c, uint32_t flags);
+// Enqueue one full bootstrap batch on `st` using scratch `sc`.
+int bootstrap_with(fdfb_ctx &c, Scratch &sc, const uint32_t *d_cts, const int32_t *d_ids, uint32_t B,
+                   uint32_t *d_out, uint32_t flags, hipStream_t st);
+
+}  // namespace fdfbi

@@ -1,0 +1,104 @@
+"""Serving engine: continuous batching under Poisson arrivals over two
+parameter sets; each request's output must be the same in the mix as alone
+(tolerance 0: the arithmetic is exact) and decrypt to f(m)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+fd = pytest.importorskip("paper_2109_02731_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_serving_mix_invariance_and_admission():
+    presets = [W.C1, W.C2]
+    ctxs = [fd.Context.keygen(p, 7000 + k) for k, p in enumerate(presets)]
+    rng = np.random.default_rng(W.ARRIVAL_SEED)
+    luts = [[W.random_lut(100 * k + j, p.t) for j in range(6)] for k, p in enumerate(presets)]
+    lids = [[c.register_lut(l) for l in ls] for c, ls in zip(ctxs, luts)]
+    # request stream: Poisson arrivals, sizes 1..48, parameter set 50/50
+    count = 40
+    times, sizes, which = W.poisson_arrivals(W.ARRIVAL_SEED, count, rate=400.0, max_batch=48)
+    reqs = []
+    for k in range(count):
+        c = int(which[k])
+        p = presets[c]
+        B = int(sizes[k])
+        msgs = rng.integers(0, p.t, B).astype(np.uint32)
+        j = int(rng.integers(0, 6))
+        cts = ctxs[c].encrypt_debug(msgs, seed=9000 + k)
+        reqs.append({"c": c, "msgs": msgs, "lut": luts[c][j], "cts": fd.to_device(cts),
+                     "ids": torch.full((B,), lids[c][j], dtype=torch.int32, device="cuda"),
+                     "out": torch.zeros((B, p.n + 1), dtype=torch.int32, device="cuda")})
+    torch.cuda.synchronize()
+    # a budget smaller than two large batches forces admission to hold work back
+    budget = 2 * (60 << 20)
+    srv = fd.Server(ctxs, max_batch=256, mem_budget=budget, nstreams=3)
+    say(f"serving: {count} requests, budget {budget >> 20} MiB")
+    ids = [None] * count
+    lat = [None] * count
+
+    def waiter():
+        for k in range(count):
+            while ids[k] is None:
+                time.sleep(1e-4)
+            lat[k] = srv.wait(ids[k])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for k, r in enumerate(reqs):
+        dt = t0 + times[k] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        ids[k] = srv.submit(r["c"], r["cts"], r["ids"], r["out"])
+    th.join(timeout=300)
+    assert not th.is_alive()
+    st = srv.stats()
+    srv.close()
+    say(f"serving stats {st}")
+    assert st["requests_done"] == count and st["bootstraps_done"] == int(sizes.sum())
+    assert st["batches"] < count  # requests were batched together
+    assert st["max_in_flight_bytes"] <= max(budget, 0) or st["batches"] == 1
+    assert all(x is not None and x > 0 for x in lat)
+
+    for k, r in enumerate(reqs):
+        c = r["c"]
+        mixed = fd.to_host(r["out"])
+        m, _ = ctxs[c].decrypt_debug(mixed)
+        assert np.array_equal(m, r["lut"][r["msgs"]]), k
+        alone = torch.zeros_like(r["out"])
+        ctxs[c].bootstrap_batch(r["cts"], r["ids"], alone)
+        torch.cuda.synchronize()
+        assert np.array_equal(fd.to_host(alone), mixed), k
+
+
+def test_server_argument_errors():
+    ctx = fd.Context.keygen(W.C1, 3)
+    ctx.register_lut(np.arange(8))
+    srv = fd.Server([ctx], max_batch=16, mem_budget=1 << 28, nstreams=1)
+    cts = torch.zeros((17, W.C1.n + 1), dtype=torch.int32, device="cuda")
+    ids = torch.zeros(17, dtype=torch.int32, device="cuda")
+    with pytest.raises(fd.FdfbError):
+        srv.submit(0, cts, ids, cts)  # larger than max_batch
+    with pytest.raises(fd.FdfbError):
+        srv.submit(1, cts[:4], ids[:4], cts[:4])  # unknown context
+    ctx.register_lut(np.zeros(8))
+    with pytest.raises(fd.FdfbError):
+        srv.submit(0, cts[:4], ids[:4], cts[:4])  # table registered after creation
+    srv.close()
