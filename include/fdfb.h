@@ -178,6 +178,18 @@ int fdfb_packing_keyswitch(fdfb_ctx *ctx, const uint32_t *d_in, uint32_t A, uint
 int fdfb_pubmux(fdfb_ctx *ctx, const uint32_t *d_rlwe, const uint32_t *d_ctN,
                 const int32_t *d_lut_ids, uint32_t B, uint32_t *d_acc, void *stream);
 
+/*
+ * Affine map on LWE samples (Sec. 2 Lemma "Linear Homomorphism of GLWE
+ * samples"; Sec. 3.4 "Computing in Z_t"): out[r] = sum_c W[r][c] * in[c]
+ * (mod 2^32) coordinate-wise, with no bootstrap.
+ *   d_W    device int32[rows][cols] weights
+ *   d_in   device uint32[cols][width] samples (width = dimension + 1)
+ *   d_out  device uint32[rows][width]
+ * Needs no context.  Errors: FDFB_EINVAL for null buffers with rows > 0.
+ */
+int fdfb_affine(const int32_t *d_W, const uint32_t *d_in, uint32_t rows, uint32_t cols, uint32_t width,
+                uint32_t *d_out, void *stream);
+
 /* ---- debug helpers (host memory, use the secret keys) ------------------ */
 
 /* Encrypt B messages m[b] in [0, t) under s: b = <a, s> + Delta m + e with a

@@ -59,7 +59,7 @@ EXPORTED = [
     "fdfb_export_keys", "fdfb_import_keys", "fdfb_get_key", "fdfb_profile", "fdfb_profile_read",
     "fdfb_set_abort", "fdfb_free", "fdfb_last_error",
     "fdfb_server_create", "fdfb_server_submit", "fdfb_server_poll", "fdfb_server_wait",
-    "fdfb_server_stats", "fdfb_server_destroy",
+    "fdfb_server_stats", "fdfb_server_destroy", "fdfb_affine",
 ]
 
 PHASES = ["modswitch_init", "sign_br", "extract_bits", "packing_ks", "pubmux", "function_br", "output"]
@@ -102,6 +102,7 @@ def lib():
             "fdfb_server_wait": (i, [P, C.c_uint64, P]),
             "fdfb_server_stats": (i, [P, P]),
             "fdfb_server_destroy": (None, [P]),
+            "fdfb_affine": (i, [P, P, u32, u32, u32, P, P]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -305,6 +306,14 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def affine(W, cts, out, stream=None):
+    """out[r] = sum_c W[r][c] * cts[c] mod 2^32 (W int32 [rows][cols] on the GPU)."""
+    rows, cols = int(W.shape[0]), int(W.shape[1])
+    _check(lib().fdfb_affine(_dev_ptr(W, "W"), _dev_ptr(cts, "cts"), rows, cols, int(cts.shape[1]),
+                             _dev_ptr(out, "out"), _stream(stream)))
+    return out
 
 
 def bootstrap_multi(jobs, stream=None):

@@ -572,6 +572,15 @@ int fdfb_pubmux(fdfb_ctx *c, const uint32_t *d_rlwe, const uint32_t *d_ctN, cons
     return FDFB_OK;
 }
 
+int fdfb_affine(const int32_t *d_W, const uint32_t *d_in, uint32_t rows, uint32_t cols, uint32_t width,
+                uint32_t *d_out, void *stream)
+{
+    if (rows == 0 || width == 0) return FDFB_OK;
+    if (!d_W || (cols && !d_in) || !d_out) return fail(FDFB_EINVAL, "null buffer");
+    K_TRY(fdfbk::launch_affine(d_W, d_in, rows, cols, width, d_out, (hipStream_t)stream));
+    return FDFB_OK;
+}
+
 int fdfb_encrypt_debug(fdfb_ctx *c, const uint32_t *m, uint32_t B, uint64_t seed, uint32_t *cts)
 {
     if (!c || (B && (!m || !cts))) return fail(FDFB_EINVAL, "null argument");

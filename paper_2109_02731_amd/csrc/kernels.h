@@ -33,6 +33,8 @@ hipError_t launch_extract(const Geometry &G, const uint32_t *acc, uint32_t A, ui
                           uint32_t add_base, uint32_t *lwe, hipStream_t s);
 hipError_t launch_keyswitch(const uint32_t *in, uint32_t B, uint32_t din, const uint32_t *key,
                             int log2B, int ell, uint32_t out_len, uint32_t *out, hipStream_t s);
+hipError_t launch_affine(const int32_t *W, const uint32_t *in, uint32_t rows, uint32_t cols, uint32_t width,
+                         uint32_t *out, hipStream_t s);
 hipError_t launch_pubmux(const Geometry &G, const uint32_t *rlwe, const uint32_t *ctN,
                          const int32_t *lut_ids, uint32_t B, const int32_t *luts, int nluts,
                          uint32_t *acc, hipStream_t s);

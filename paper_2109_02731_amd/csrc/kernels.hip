@@ -137,6 +137,35 @@ __global__ __launch_bounds__(256) void k_keyswitch(const uint32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Affine map on LWE samples (Sec. 2 Lemma "Linear Homomorphism of GLWE
+// samples" with scalar weights): out[r] = sum_c W[r][c] in[c] (mod 2^32),
+// every coordinate of the samples at once.  Workgroup: AF_ROWS output rows x
+// 256 words; each input word is read once per workgroup.
+// ---------------------------------------------------------------------------
+constexpr int AF_ROWS = 8;
+
+__global__ __launch_bounds__(256) void k_affine(const int32_t *__restrict__ W, const uint32_t *__restrict__ in,
+                                                uint32_t rows, uint32_t cols, uint32_t width,
+                                                uint32_t *__restrict__ out)
+{
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t r0 = blockIdx.y * AF_ROWS;
+    if (k >= width) return;
+    uint32_t acc[AF_ROWS];
+#pragma unroll
+    for (int r = 0; r < AF_ROWS; ++r) acc[r] = 0;
+    for (uint32_t c = 0; c < cols; ++c) {
+        const uint32_t x = in[(size_t)c * width + k];
+#pragma unroll
+        for (int r = 0; r < AF_ROWS; ++r)
+            if (r0 + r < rows) acc[r] += (uint32_t)W[(size_t)(r0 + r) * cols + c] * x;
+    }
+#pragma unroll
+    for (int r = 0; r < AF_ROWS; ++r)
+        if (r0 + r < rows) out[(size_t)(r0 + r) * width + k] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
 // PubMux of the bootstrap (Sec. 3.1 Fig. 1 with the selection of Fig. 2):
 //   p_A = rotP_1 X^{b_N}, p_B = rotP_0 X^{b_N}, delta = (p_B - p_A) mod t,
 //   acc = [Delta p_A, 0] + sum_i digit_i(delta) * R_i.
@@ -522,6 +551,15 @@ hipError_t launch_keyswitch(const uint32_t *in, uint32_t B, uint32_t din, const 
     if (ell > 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_keyswitch, dim3((out_len + 255) / 256, (B + KS_TB - 1) / KS_TB), dim3(256),
                        0, s, in, B, din, key, log2B, ell, out_len, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_affine(const int32_t *W, const uint32_t *in, uint32_t rows, uint32_t cols, uint32_t width,
+                         uint32_t *out, hipStream_t s)
+{
+    if (!rows || !width) return hipSuccess;
+    hipLaunchKernelGGL(k_affine, dim3((width + 255) / 256, (rows + AF_ROWS - 1) / AF_ROWS), dim3(256), 0, s, W, in,
+                       rows, cols, width, out);
     return hipGetLastError();
 }
 

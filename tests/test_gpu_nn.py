@@ -1,0 +1,71 @@
+"""NN-shaped circuit on ciphertexts: x in Z_32^784 -> dense 784->128 ->
+FDFB ReLU (extracted output, Sec. 3.4 "Computing in Z_t") -> dense 128->10
+on c_Q -> key switch.  Every value is checked against plaintext Z_32
+evaluation; affine maps and key switch bit for bit against the oracle, and
+sampled bootstraps bit for bit against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+fd = pytest.importorskip("paper_2109_02731_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_nn_circuit_784_128_10():
+    p = W.C4
+    n, N, t = p.n, p.N, p.t
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C4"])
+    relu = W.named_luts(t)["relu"]
+    lid = ctx.register_lut(relu)
+    x, w1, w2 = W.nn_inputs(W.MSG_SEED["C4"], t)
+    cts = ctx.encrypt_debug(x, seed=W.MSG_SEED["C4"])
+    d_w1 = torch.from_numpy(w1).cuda()
+    d_w2 = torch.from_numpy(w2).cuda()
+    h = torch.empty((128, n + 1), dtype=torch.int32, device="cuda")
+    hq = torch.empty((128, N + 1), dtype=torch.int32, device="cuda")
+    y = torch.empty((10, N + 1), dtype=torch.int32, device="cuda")
+    yo = torch.empty((10, n + 1), dtype=torch.int32, device="cuda")
+    say("nn: affine 784->128, FDFB ReLU x128, affine 128->10, key switch")
+    fd.affine(d_w1, fd.to_device(cts), h)
+    ctx.bootstrap_batch(h, torch.full((128,), lid, dtype=torch.int32, device="cuda"), hq,
+                        flags=fd.OUT_EXTRACTED)
+    fd.affine(d_w2, hq, y)
+    ctx.keyswitch(y, yo)
+    torch.cuda.synchronize()
+    h_, hq_, y_, yo_ = (fd.to_host(a) for a in (h, hq, y, yo))
+
+    # plaintext evaluation over Z_32 (two's-complement ReLU)
+    hp = (w1.astype(np.int64) @ x.astype(np.int64)) % t
+    rp = relu[hp]
+    yp = (w2.astype(np.int64) @ rp.astype(np.int64)) % t
+    assert np.array_equal(ctx.decrypt_debug(h_)[0], hp)
+    assert np.array_equal(ctx.decrypt_debug(hq_)[0], rp)
+    assert np.array_equal(ctx.decrypt_debug(yo_)[0], yp)
+
+    # oracle, bit for bit
+    ok = oracle.keygen(p, W.KEY_SEED["C4"])
+    assert np.array_equal(h_, oracle.affine(w1, cts))
+    assert np.array_equal(y_, oracle.affine(w2, hq_))
+    for r in range(10):
+        assert np.array_equal(yo_[r], oracle.keyswitch(y_[r], ok.ksk, p.ks_log2B, p.ks_ell, n + 1))
+    r0, r1 = oracle.setup_polynomial(relu, N)
+    from concurrent.futures import ThreadPoolExecutor
+    sample = [77]
+    with ThreadPoolExecutor(len(sample)) as ex:
+        refs = list(ex.map(lambda k: oracle.fdfb(ok, r0, r1, h_[k], flags=oracle.OUT_EXTRACTED), sample))
+    for k, ref in zip(sample, refs):
+        assert np.array_equal(hq_[k], ref), k
