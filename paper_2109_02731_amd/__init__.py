@@ -16,7 +16,9 @@ import os
 
 import numpy as np
 
-from ._build import LIB as _LIB_PATH, build as _build
+from . import _build as _buildmod
+
+_LIB_PATH = _buildmod.LIB
 
 OUT_EXTRACTED = 0x1
 PLAIN = 0x2
@@ -71,7 +73,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            _build()
+            _buildmod.build()
         L = C.CDLL(_LIB_PATH)
         P, u32, u64, sz = C.c_void_p, C.c_uint32, C.c_uint64, C.c_size_t
         i = C.c_int

@@ -285,6 +285,29 @@ std::vector<int8_t> build_brk_fragments(const fdfb_ctx &c)
     return out;
 }
 
+// Lane-ordered B fragments of the MFMA key switch: block (kb, tile) holds,
+// for lane L and byte t, limb L % 4 of key word K[i][j][4 tile + L/4 % 4]
+// with j * din + i = 64 kb + 16 (L / 16) + t; words past out_len are zero.
+std::vector<int8_t> build_ks_fragments(const uint32_t *key, uint32_t din, uint32_t ell, uint32_t out_len)
+{
+    const uint32_t nkb = din * ell / 64, wtiles = (out_len + 63) / 64 * 16;
+    std::vector<int8_t> out((size_t)nkb * wtiles * 1024);
+    parallel_for((size_t)nkb * wtiles, [&](size_t id) {
+        const uint32_t kb = id / wtiles, tile = id % wtiles;
+        for (uint32_t L = 0; L < 64; ++L) {
+            const uint32_t col = L & 15, w = 4 * tile + (col >> 2), l = col & 3;
+            int8_t *dst = &out[(id * 64 + L) * 16];
+            for (uint32_t t = 0; t < 16; ++t) {
+                const uint32_t k = 64 * kb + 16 * (L >> 4) + t, j = k / din, i = k % din;
+                int8_t limbs[4] = {0, 0, 0, 0};
+                if (w < out_len) balanced_limbs(key[((size_t)i * ell + j) * out_len + w], limbs);
+                dst[t] = limbs[l];
+            }
+        }
+    });
+    return out;
+}
+
 template <class T>
 int dev_upload(T **dst, const T *src, size_t count)
 {
@@ -308,8 +331,23 @@ int ensure_device(fdfb_ctx &c)
     if (!c.on_device) {
         int rc;
         if ((rc = dev_upload(&c.d_brk, c.brk.data(), c.brk.size()))) return rc;
-        if ((rc = dev_upload(&c.d_pk, c.pk.data(), c.pk.size()))) return rc;
-        if ((rc = dev_upload(&c.d_ksk, c.ksk.data(), c.ksk.size()))) return rc;
+        const fdfb_params &P = c.P;
+        if (fdfbk::keyswitch_mfma_supported(P.pk_log2B, P.pk_ell, P.N)) {
+            std::vector<int8_t> fr = build_ks_fragments(c.pk.data(), P.N, P.pk_ell, 2 * P.N);
+            int8_t *p = nullptr;
+            if ((rc = dev_upload(&p, fr.data(), fr.size()))) return rc;
+            c.d_pk_frag = p;
+        } else if ((rc = dev_upload(&c.d_pk, c.pk.data(), c.pk.size()))) {
+            return rc;
+        }
+        if (fdfbk::keyswitch_mfma_supported(P.ks_log2B, P.ks_ell, P.N)) {
+            std::vector<int8_t> fr = build_ks_fragments(c.ksk.data(), P.N, P.ks_ell, P.n + 1);
+            int8_t *p = nullptr;
+            if ((rc = dev_upload(&p, fr.data(), fr.size()))) return rc;
+            c.d_ksk_frag = p;
+        } else if ((rc = dev_upload(&c.d_ksk, c.ksk.data(), c.ksk.size()))) {
+            return rc;
+        }
         if (c.mfma_ok) {
             std::vector<int8_t> fr = build_brk_fragments(c);
             int8_t *p = nullptr;
@@ -372,6 +410,18 @@ hipError_t run_br(fdfb_ctx &c, uint32_t *acc, const uint32_t *ctN, uint32_t A, u
     return fdfbk::launch_br_plain(c.geom, acc, ctN, A, per, c.d_brk, st);
 }
 
+// LWE -> LWE (ksK) or LWE -> RLWE (pK) switching of B samples of dimension N,
+// on int8 MFMA when the key was uploaded as fragments.
+hipError_t run_ks(fdfb_ctx &c, bool packing, const uint32_t *in, uint32_t B, uint32_t *out, hipStream_t st)
+{
+    const fdfb_params &P = c.P;
+    const int lb = packing ? P.pk_log2B : P.ks_log2B, ell = packing ? P.pk_ell : P.ks_ell;
+    const uint32_t out_len = packing ? 2 * P.N : P.n + 1;
+    const void *frag = packing ? c.d_pk_frag : c.d_ksk_frag;
+    if (frag) return fdfbk::launch_keyswitch_mfma(in, B, P.N, frag, lb, ell, out_len, out, st);
+    return fdfbk::launch_keyswitch(in, B, P.N, packing ? c.d_pk : c.d_ksk, lb, ell, out_len, out, st);
+}
+
 // The requested blind-rotation form must exist for the context's parameters.
 int check_form(const fdfb_ctx &c, uint32_t flags)
 {
@@ -414,7 +464,7 @@ int bootstrap_with(fdfb_ctx &c, Scratch &sc, const uint32_t *d_cts, const int32_
     K_TRY(fdfbk::launch_extract(G, sc.acc_sign, B * eb, eb, half, sc.cbits, st));
     K_TRY(mark(3));
     // 4. BuildAcc: LWE -> RLWE switching, then the public mux
-    K_TRY(fdfbk::launch_keyswitch(sc.cbits, B * eb, N, c.d_pk, G.pk_log2B, G.pk_ell, 2 * N, sc.rbits, st));
+    K_TRY(run_ks(c, true, sc.cbits, B * eb, sc.rbits, st));
     K_TRY(mark(4));
     K_TRY(fdfbk::launch_pubmux(G, sc.rbits, sc.ctN, d_ids, B, c.d_luts, c.nluts, sc.accf, st));
     K_TRY(mark(5));
@@ -426,7 +476,7 @@ int bootstrap_with(fdfb_ctx &c, Scratch &sc, const uint32_t *d_cts, const int32_
         K_TRY(fdfbk::launch_extract(G, sc.accf, B, 1, 0, d_out, st));
     } else {
         K_TRY(fdfbk::launch_extract(G, sc.accf, B, 1, 0, sc.cq, st));
-        K_TRY(fdfbk::launch_keyswitch(sc.cq, B, N, c.d_ksk, G.ks_log2B, G.ks_ell, G.n + 1, d_out, st));
+        K_TRY(run_ks(c, false, sc.cq, B, d_out, st));
     }
     K_TRY(mark(7));
     return FDFB_OK;
@@ -509,8 +559,7 @@ int fdfb_keyswitch(fdfb_ctx *c, const uint32_t *d_in, uint32_t B, uint32_t *d_ou
     if (!d_in || !d_out) return fail(FDFB_EINVAL, "null buffer");
     int rc = ensure_device(*c);
     if (rc) return rc;
-    K_TRY(fdfbk::launch_keyswitch(d_in, B, c->P.N, c->d_ksk, c->P.ks_log2B, c->P.ks_ell, c->P.n + 1, d_out,
-                                  (hipStream_t)stream));
+    K_TRY(run_ks(*c, false, d_in, B, d_out, (hipStream_t)stream));
     return FDFB_OK;
 }
 
@@ -554,8 +603,7 @@ int fdfb_packing_keyswitch(fdfb_ctx *c, const uint32_t *d_in, uint32_t A, uint32
     if (!d_in || !d_out) return fail(FDFB_EINVAL, "null buffer");
     int rc = ensure_device(*c);
     if (rc) return rc;
-    K_TRY(fdfbk::launch_keyswitch(d_in, A, c->P.N, c->d_pk, c->P.pk_log2B, c->P.pk_ell, 2 * c->P.N, d_out,
-                                  (hipStream_t)stream));
+    K_TRY(run_ks(*c, true, d_in, A, d_out, (hipStream_t)stream));
     return FDFB_OK;
 }
 

@@ -33,6 +33,11 @@ hipError_t launch_extract(const Geometry &G, const uint32_t *acc, uint32_t A, ui
                           uint32_t add_base, uint32_t *lwe, hipStream_t s);
 hipError_t launch_keyswitch(const uint32_t *in, uint32_t B, uint32_t din, const uint32_t *key,
                             int log2B, int ell, uint32_t out_len, uint32_t *out, hipStream_t s);
+// Key switching as an int8 MFMA GEMM over key fragments built by
+// build_keyswitch_fragments (requires log2B <= 7 and din % 64 == 0).
+bool keyswitch_mfma_supported(int log2B, int ell, uint32_t din);
+hipError_t launch_keyswitch_mfma(const uint32_t *in, uint32_t B, uint32_t din, const void *kfrag, int log2B,
+                                 int ell, uint32_t out_len, uint32_t *out, hipStream_t s);
 hipError_t launch_affine(const int32_t *W, const uint32_t *in, uint32_t rows, uint32_t cols, uint32_t width,
                          uint32_t *out, hipStream_t s);
 hipError_t launch_pubmux(const Geometry &G, const uint32_t *rlwe, const uint32_t *ctN,

@@ -137,6 +137,98 @@ __global__ __launch_bounds__(256) void k_keyswitch(const uint32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Key switching on int8 MFMA: the same sum as k_keyswitch as a GEMM
+//   C[b][(w, l)] = sum_k dig[b][k] * limb_l(K[k][w]),  k = j * din + i
+// (digit j of input coordinate i), with the key split into balanced byte
+// limbs and stored as lane-ordered 1 KB B fragments per (k-block, 4 words).
+// Workgroup: 64 samples x 64 output words; wavefront w takes words
+// [16 w, 16 w + 16) for all 64 samples (4 x 4 MFMA tiles).  Digits of a
+// 64-coordinate chunk are staged in LDS as bytes; int32 sums are exact
+// (din ell 15 128 < 2^31) and limbs recombine mod 2^32 by DPP quad sums.
+// ---------------------------------------------------------------------------
+template <int ELL>
+__global__ __launch_bounds__(256) void k_keyswitch_mfma(const uint32_t *__restrict__ in, uint32_t B,
+                                                        uint32_t din, const v4i *__restrict__ kfrag,
+                                                        int log2B, uint32_t out_len, uint32_t wtiles,
+                                                        uint32_t *__restrict__ out)
+{
+    constexpr int ROW = 80;  // bytes per staged sample row (64 digits + pad, conflict-free reads)
+    __shared__ __attribute__((aligned(16))) uint8_t dig[ELL][64][ROW];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t s0 = blockIdx.y * 64;
+    const uint32_t wt0 = blockIdx.x * 16 + wv * 4;  // first 4-word tile of this wavefront
+    const uint32_t drop = 32 - ELL * log2B;
+    const uint32_t dmask = (1u << log2B) - 1;
+    const int ri = lane & 15, g = lane >> 4;
+    v4i C[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) C[a][b] = v4i{0, 0, 0, 0};
+
+    for (uint32_t c0 = 0; c0 < din; c0 += 64) {
+        v4i Bf[ELL][4];
+#pragma unroll
+        for (int j = 0; j < ELL; ++j) {
+            const uint32_t kb = (j * din + c0) / 64;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) Bf[j][nt] = kfrag[((size_t)kb * wtiles + wt0 + nt) * 64 + lane];
+        }
+        __syncthreads();  // the previous chunk's digits are no longer read
+        for (int task = threadIdx.x; task < 64 * 16; task += 256) {
+            const uint32_t sl = task >> 4, cq = (task & 15) * 4;
+            const uint32_t b = s0 + sl;
+            uint32_t x[4] = {0, 0, 0, 0};
+            if (b < B) {
+                const uint32_t *src = in + (size_t)b * (din + 1) + 1 + c0 + cq;
+                x[0] = src[0]; x[1] = src[1]; x[2] = src[2]; x[3] = src[3];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = drop ? (x[u] + (1u << (drop - 1))) >> drop : x[u];
+            if (b >= B) x[0] = x[1] = x[2] = x[3] = 0;
+#pragma unroll
+            for (int j = 0; j < ELL; ++j) {
+                const uint32_t sh = log2B * j;
+                const uint32_t w = ((x[0] >> sh) & dmask) | (((x[1] >> sh) & dmask) << 8) |
+                                   (((x[2] >> sh) & dmask) << 16) | (((x[3] >> sh) & dmask) << 24);
+                *(uint32_t *)&dig[j][sl][cq] = w;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ELL; ++j) {
+            v4i Af[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) Af[mt] = *(const v4i *)&dig[j][mt * 16 + ri][16 * g];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    C[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Af[mt], Bf[j][nt], C[mt][nt], 0, 0, 0);
+        }
+    }
+    // recombine limbs: column = (word within tile, limb); rows = samples
+    const int limb = lane & 3, wq = (lane >> 2) & 3;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int x = (int)((uint32_t)C[mt][nt][v] << (8 * limb));
+                x += __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);
+                x += __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);
+                const uint32_t b = s0 + mt * 16 + 4 * g + v;
+                const uint32_t w = (wt0 + nt) * 4 + wq;
+                if (limb == 0 && b < B && w < out_len) {
+                    const uint32_t init = (w == 0) ? in[(size_t)b * (din + 1)] : 0u;
+                    out[(size_t)b * out_len + w] = init - (uint32_t)x;
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
 // Affine map on LWE samples (Sec. 2 Lemma "Linear Homomorphism of GLWE
 // samples" with scalar weights): out[r] = sum_c W[r][c] in[c] (mod 2^32),
 // every coordinate of the samples at once.  Workgroup: AF_ROWS output rows x
@@ -551,6 +643,31 @@ hipError_t launch_keyswitch(const uint32_t *in, uint32_t B, uint32_t din, const 
     if (ell > 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_keyswitch, dim3((out_len + 255) / 256, (B + KS_TB - 1) / KS_TB), dim3(256),
                        0, s, in, B, din, key, log2B, ell, out_len, out);
+    return hipGetLastError();
+}
+
+bool keyswitch_mfma_supported(int log2B, int ell, uint32_t din)
+{
+    return log2B <= 7 && ell >= 1 && ell <= 8 && din % 64 == 0;
+}
+
+hipError_t launch_keyswitch_mfma(const uint32_t *in, uint32_t B, uint32_t din, const void *kfrag, int log2B,
+                                 int ell, uint32_t out_len, uint32_t *out, hipStream_t s)
+{
+    if (!B) return hipSuccess;
+    const uint32_t words_pad = (out_len + 63) / 64 * 64;
+    const dim3 grid(words_pad / 64, (B + 63) / 64);
+    const v4i *kf = (const v4i *)kfrag;
+    switch (ell) {
+#define KS_CASE(L)                                                                                   \
+    case L:                                                                                          \
+        hipLaunchKernelGGL(k_keyswitch_mfma<L>, grid, dim3(256), 0, s, in, B, din, kf, log2B, out_len, \
+                           words_pad / 4, out);                                                      \
+        break;
+        KS_CASE(1) KS_CASE(2) KS_CASE(3) KS_CASE(4) KS_CASE(5) KS_CASE(6) KS_CASE(7) KS_CASE(8)
+#undef KS_CASE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
