@@ -250,37 +250,32 @@ void setup_polynomial(const uint32_t *f, uint32_t t, uint32_t N, int32_t *p0, in
         }
 }
 
-// Lane-ordered B fragments of the MFMA blind rotation: block (i, r', kb, j)
-// holds, for lane L and byte t, limb l of K'~[64 kb + 16 g + t + 16 s] where
-// (s, l) = (L/4 % 4, L % 4) of column L % 16, g = L / 16, K' the key polynomial
-// of virtual row r' for output component j, times 2^(7h) for digit chunk h,
-// and K'~ its negacyclic extension.
+// Key operand of the MFMA blind rotation, as byte planes: block (i, r', j)
+// holds 4 planes of N + 64 bytes, plane l = limb l of K'~[x] for x < N + 64,
+// where K' is the key polynomial of virtual row r' for output component j,
+// times 2^(7h) for digit chunk h, and K'~ its negacyclic extension.  Lane
+// (s, l, g) of k-block kb reads bytes 64 kb + 16 (g + s) .. +15 of plane l.
 std::vector<int8_t> build_brk_fragments(const fdfb_ctx &c)
 {
     const fdfb_params &P = c.P;
     const uint32_t N = P.N, ell = P.g_ell, CH = fdfbk::digit_chunks(P.g_log2B);
-    const uint32_t RPC = ell * CH, RV = 2 * RPC, NKB = N / 64, R = 2 * ell;
-    std::vector<int8_t> out((size_t)P.n * RV * NKB * 2 * 1024);
+    const uint32_t RPC = ell * CH, RV = 2 * RPC, R = 2 * ell, PL = N + 64;
+    std::vector<int8_t> out((size_t)P.n * RV * 2 * 4 * PL);
     parallel_for((size_t)P.n * RV, [&](size_t id) {
         const uint32_t i = id / RV, rv = id % RV;
         const uint32_t comp_in = rv / RPC, rr = rv % RPC, jd = rr / CH, h = rr % CH;
         const uint32_t row = comp_in * ell + jd;
-        for (uint32_t kb = 0; kb < NKB; ++kb)
-            for (uint32_t j = 0; j < 2; ++j) {
-                const uint32_t *K = &c.brk[(((size_t)i * R + row) * 2 + j) * N];
-                for (uint32_t L = 0; L < 64; ++L) {
-                    const uint32_t col = L & 15, s = col >> 2, l = col & 3, g = L >> 4;
-                    int8_t *dst = &out[(((id * NKB + kb) * 2 + j) * 64 + L) * 16];
-                    for (uint32_t t = 0; t < 16; ++t) {
-                        const uint32_t x = 64 * kb + 16 * g + t + 16 * s;  // < N + 64
-                        uint32_t w = (x < N) ? K[x] : 0u - K[x - N];
-                        w <<= 7 * h;
-                        int8_t limbs[4];
-                        balanced_limbs(w, limbs);
-                        dst[t] = limbs[l];
-                    }
-                }
+        for (uint32_t j = 0; j < 2; ++j) {
+            const uint32_t *K = &c.brk[(((size_t)i * R + row) * 2 + j) * N];
+            int8_t *dst = &out[(id * 2 + j) * 4 * PL];
+            for (uint32_t x = 0; x < PL; ++x) {
+                uint32_t w = (x < N) ? K[x] : 0u - K[x - N];  // PL <= 2N
+                w <<= 7 * h;
+                int8_t limbs[4];
+                balanced_limbs(w, limbs);
+                for (uint32_t l = 0; l < 4; ++l) dst[l * PL + x] = limbs[l];
             }
+        }
     });
     return out;
 }

@@ -419,6 +419,7 @@ struct BrMfma {
     static constexpr int NDIAG = NT + KC - 1;        // local diagonals per unit
     static constexpr int DIG_WORDS = N / 2;          // one digit row: 2N bytes
     static constexpr size_t LDS_BYTES = 4 * (2 * (size_t)N + 2 * (size_t)RV * DIG_WORDS);
+    static constexpr int PLV = (N + 64) / 16;        // one key limb plane, in 16-byte units
 };
 
 template <int N, int ELL, int CH>
@@ -451,10 +452,12 @@ __global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
     const int S0 = N - 1 - ri + 16 * g;
     // recombination: this lane's output column (shift s, limb l)
     const int limb = lane & 3, ss = (lane >> 2) & 3;
-    // B fragments of unit u = (row, chunk) for this wavefront's component
+    // B fragments of unit u = (row, chunk) for this wavefront's component:
+    // lane (s, l, g) reads 16 bytes of limb plane l at 64 kb + 16 (g + s)
+    const int lane_v = (lane & 3) * G::PLV + (lane >> 4) + ((lane >> 2) & 3);
     auto frag = [&](int i, int u) {
         const int r = u / G::NCH, c = u % G::NCH;
-        return bfrag + ((size_t)(i * G::RV + r) * G::NKB * 2 + c * G::KC * 2 + jc) * 64 + lane;
+        return bfrag + ((size_t)(i * G::RV + r) * 2 + jc) * 4 * G::PLV + lane_v + c * G::KC * 4;
     };
     auto next_live = [&](int i) {
         int k = i + 1;
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
     {
         const v4i *bp = frag(i < n ? i : 0, 0);
 #pragma unroll
-        for (int kb = 0; kb < G::KC; ++kb) B0[kb] = bp[kb * 128];
+        for (int kb = 0; kb < G::KC; ++kb) B0[kb] = bp[kb * 4];
     }
     int set = 0;
     __syncthreads();
@@ -538,7 +541,7 @@ __global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
             // the scheduling barrier keeps the loads here, a full unit ahead
             const v4i *np = (u + 1 < G::UNITS) ? frag(i, u + 1) : frag(inext < n ? inext : i, 0);
 #pragma unroll
-            for (int kb = 0; kb < G::KC; ++kb) Bn[kb] = np[kb * 128];
+            for (int kb = 0; kb < G::KC; ++kb) Bn[kb] = np[kb * 4];
             __builtin_amdgcn_sched_barrier(0);
             // Toeplitz fragments, one per diagonal, ping-ponged: the words of
             // diagonal dd+1 are read and aligned while diagonal dd's MFMAs run.
