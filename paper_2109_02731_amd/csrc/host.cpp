@@ -10,6 +10,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <cstdlib>
 #include <vector>
 
 #include "fdfb.h"
@@ -303,6 +304,76 @@ std::vector<int8_t> build_ks_fragments(const uint32_t *key, uint32_t din, uint32
     return out;
 }
 
+// Key operand of the Karatsuba blind rotation: block (i, r', p, j) holds 4
+// byte planes of M + 64 bytes (M = N/2) for the half-ring key polynomial of
+// product p: K_e[x] = K[2x], K_o[x] = K[2x+1] or K_e + K_o, negacyclically
+// extended in Z[Y]/(Y^M + 1), times 2^(7h) for digit chunk h.
+std::vector<int8_t> build_brk_kara(const fdfb_ctx &c)
+{
+    const fdfb_params &P = c.P;
+    const uint32_t N = P.N, M = N / 2, ell = P.g_ell, CH = fdfbk::digit_chunks(P.g_log2B);
+    const uint32_t RPC = ell * CH, RV = 2 * RPC, R = 2 * ell, PL = M + 64;
+    std::vector<int8_t> out((size_t)P.n * RV * 3 * 2 * 4 * PL);
+    parallel_for((size_t)P.n * RV, [&](size_t id) {
+        const uint32_t i = id / RV, rv = id % RV;
+        const uint32_t comp_in = rv / RPC, rr = rv % RPC, jd = rr / CH, h = rr % CH;
+        const uint32_t row = comp_in * ell + jd;
+        for (uint32_t j = 0; j < 2; ++j) {
+            const uint32_t *K = &c.brk[(((size_t)i * R + row) * 2 + j) * N];
+            for (uint32_t p = 0; p < 3; ++p) {
+                int8_t *dst = &out[((id * 3 + p) * 2 + j) * 4 * PL];
+                for (uint32_t x = 0; x < PL; ++x) {  // PL <= 2M
+                    const uint32_t xx = x < M ? x : x - M;
+                    uint32_t w = p == 0 ? K[2 * xx] : p == 1 ? K[2 * xx + 1] : K[2 * xx] + K[2 * xx + 1];
+                    if (x >= M) w = 0u - w;
+                    w <<= 7 * h;
+                    int8_t limbs[4];
+                    balanced_limbs(w, limbs);
+                    for (uint32_t l = 0; l < 4; ++l) dst[l * PL + x] = limbs[l];
+                }
+            }
+        }
+    });
+    return out;
+}
+
+// Offset correction of the Karatsuba form: the kernel multiplies V = D - O,
+// with O = 64 on even and 63 on odd coefficients for 7-bit digit chunks (0
+// for narrower chunks), so sum_r O_r * K'_r (negacyclic, mod 2^32) is added
+// back per step.  Stored per (i, j) in even/odd order.  With s_c / t_c the
+// partial / total sums of K' over coefficients of parity c,
+//   (O * K')[m] = o_e (2 s_same - t_same) + o_o (2 s_other - t_other).
+std::vector<uint32_t> build_brk_kara_corr(const fdfb_ctx &c)
+{
+    const fdfb_params &P = c.P;
+    const uint32_t N = P.N, M = N / 2, ell = P.g_ell, CH = fdfbk::digit_chunks(P.g_log2B);
+    const uint32_t RPC = ell * CH, RV = 2 * RPC, R = 2 * ell;
+    std::vector<uint32_t> out((size_t)P.n * 2 * N);
+    parallel_for((size_t)P.n * 2, [&](size_t id) {
+        const uint32_t i = id / 2, j = id % 2;
+        std::vector<uint32_t> W(N, 0), Kp(N);
+        for (uint32_t rv = 0; rv < RV; ++rv) {
+            const uint32_t comp_in = rv / RPC, rr = rv % RPC, jd = rr / CH, h = rr % CH;
+            if (7 * (h + 1) > P.g_log2B) continue;  // narrow chunk: no offset
+            const uint32_t oe = 64, oo = 63;
+            const uint32_t *K = &c.brk[(((size_t)i * R + comp_in * ell + jd) * 2 + j) * N];
+            uint32_t tot[2] = {0, 0}, part[2] = {0, 0};
+            for (uint32_t x = 0; x < N; ++x) {
+                Kp[x] = K[x] << (7 * h);
+                tot[x & 1] += Kp[x];
+            }
+            for (uint32_t m = 0; m < N; ++m) {
+                part[m & 1] += Kp[m];
+                const uint32_t same = 2 * part[m & 1] - tot[m & 1];
+                const uint32_t other = 2 * part[(m & 1) ^ 1] - tot[(m & 1) ^ 1];
+                W[m] += oe * same + oo * other;
+            }
+        }
+        for (uint32_t m = 0; m < N; ++m) out[id * N + (m & 1) * M + (m >> 1)] = W[m];
+    });
+    return out;
+}
+
 template <class T>
 int dev_upload(T **dst, const T *src, size_t count)
 {
@@ -344,10 +415,17 @@ int ensure_device(fdfb_ctx &c)
             return rc;
         }
         if (c.mfma_ok) {
-            std::vector<int8_t> fr = build_brk_fragments(c);
+            // FDFB_BR_FORM=direct selects the four-block form (comparison runs)
+            const char *form = std::getenv("FDFB_BR_FORM");
+            c.kara = !(form && std::string(form) == "direct");
+            std::vector<int8_t> fr = c.kara ? build_brk_kara(c) : build_brk_fragments(c);
             int8_t *p = nullptr;
             if ((rc = dev_upload(&p, fr.data(), fr.size()))) return rc;
             c.d_brk_frag = p;
+            if (c.kara) {
+                std::vector<uint32_t> corr = build_brk_kara_corr(c);
+                if ((rc = dev_upload(&c.d_brk_corr, corr.data(), corr.size()))) return rc;
+            }
         }
         c.on_device = true;
     }
@@ -401,7 +479,8 @@ hipError_t run_br(fdfb_ctx &c, uint32_t *acc, const uint32_t *ctN, uint32_t A, u
                   uint32_t flags, hipStream_t st)
 {
     if (!(flags & FDFB_PLAIN) && c.mfma_ok)
-        return fdfbk::launch_br_mfma(c.geom, acc, ctN, A, per, c.d_brk_frag, st);
+        return c.kara ? fdfbk::launch_br_kara(c.geom, acc, ctN, A, per, c.d_brk_frag, c.d_brk_corr, st)
+                      : fdfbk::launch_br_mfma(c.geom, acc, ctN, A, per, c.d_brk_frag, st);
     return fdfbk::launch_br_plain(c.geom, acc, ctN, A, per, c.d_brk, st);
 }
 

@@ -35,10 +35,12 @@ struct fdfb_ctx {
 
     fdfbk::Geometry geom{};
     bool mfma_ok = false;
+    bool kara = false;  // MFMA blind rotation in its Karatsuba form (set at upload)
 
     bool on_device = false;
     uint32_t *d_brk = nullptr, *d_pk = nullptr, *d_ksk = nullptr;
     void *d_brk_frag = nullptr;
+    uint32_t *d_brk_corr = nullptr;  // Karatsuba form: offset correction per (i, j)
     void *d_pk_frag = nullptr, *d_ksk_frag = nullptr;  // int8 MFMA key-switch fragments
     int32_t *d_luts = nullptr;
     int dev_nluts = 0;
@@ -54,7 +56,7 @@ struct fdfb_ctx {
     {
         for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
         scratch.release();
-        for (void *p : {(void *)d_brk, (void *)d_pk, (void *)d_ksk, d_brk_frag, d_pk_frag, d_ksk_frag,
+        for (void *p : {(void *)d_brk, (void *)d_pk, (void *)d_ksk, d_brk_frag, (void *)d_brk_corr, d_pk_frag, d_ksk_frag,
                         (void *)d_luts})
             if (p) (void)hipFree(p);
     }

@@ -28,6 +28,10 @@ hipError_t launch_br_plain(const Geometry &G, uint32_t *acc, const uint32_t *ctN
                            uint32_t accs_per_ct, const uint32_t *brk_raw, hipStream_t s);
 hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
                           uint32_t accs_per_ct, const void *brk_frag, hipStream_t s);
+// Karatsuba form of the batched blind rotation (same instantiations as
+// launch_br_mfma): brk_frag from build_brk_kara, corr the offset table.
+hipError_t launch_br_kara(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
+                          uint32_t accs_per_ct, const void *brk_frag, const uint32_t *corr, hipStream_t s);
 // add_base != 0: sample b of accumulator a gets add_base * L_boot^(a % per) added.
 hipError_t launch_extract(const Geometry &G, const uint32_t *acc, uint32_t A, uint32_t per,
                           uint32_t add_base, uint32_t *lwe, hipStream_t s);

@@ -605,6 +605,307 @@ __global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
 }
 
 // ---------------------------------------------------------------------------
+// Blind rotation with one level of Karatsuba over the even/odd split.
+// With Y = X^2 (Y^(N/2) = -1) a polynomial is a = a_e(Y) + X a_o(Y), and
+//   (a b)_e = a_e b_e + Y a_o b_o
+//   (a b)_o = (a_e + a_o)(b_e + b_o) - a_e b_e - a_o b_o,
+// three negacyclic products of size M = N/2 instead of four quarter-size
+// blocks of the full product.  The digit operand of the middle product is
+// a_e + a_o, which must fit int8: 7-bit digits are offset to V_e = D_e - 64
+// and V_o = D_o - 63 (V_e, V_o, V_e + V_o and their negations all lie in
+// [-127, 127]), and sum_r O_r * K_r, the product of the offset polynomials
+// with the key rows, is added back each step from a table built with the
+// key.  Narrower digit chunks need no offset.  The three products
+// accumulate in three register sets over all digit rows; the accumulator
+// is kept in LDS in even/odd order, where X^(-a) acts on each half as a
+// negacyclic rotation of size M (and swaps the halves for odd a).
+// Everything else (Toeplitz A fragments per diagonal, 4 key shifts x 4
+// limbs as the 16 B columns, planar key limbs, unit double buffering) is
+// as in k_br_mfma, at size M.
+// ---------------------------------------------------------------------------
+template <int V> struct IC { static constexpr int value = V; };
+template <int I, int END> struct StaticFor {
+    template <class F> __device__ __attribute__((always_inline)) static void run(F &&f)
+    {
+        f(IC<I>{});
+        StaticFor<I + 1, END>::run(f);
+    }
+};
+template <int END> struct StaticFor<END, END> {
+    template <class F> __device__ __attribute__((always_inline)) static void run(F &&) {}
+};
+
+template <int N, int ELL, int CH>
+struct BrKara {
+    static constexpr int M = N / 2;                   // size of the half rings
+    static constexpr int RPC = ELL * CH;              // virtual digit rows per component
+    static constexpr int RV = 2 * RPC;                // virtual digit rows per CMux
+    static constexpr int WPC = N > 1024 ? 2 : 1;      // wavefronts per output component
+    static constexpr int WAVES = 2 * WPC;
+    static constexpr int NT = M / 64 / WPC;           // output tiles per wavefront and product
+    static constexpr int NKB = M / 64;                // k-blocks per product
+    static constexpr int KC = NKB < 8 ? NKB : 8;      // k-blocks per key chunk
+    static constexpr int NCH = NKB / KC;              // key chunks per product
+    static constexpr int UPR = 3 * NCH;               // units per digit row
+    static constexpr int RSTEP = (UPR % 2) ? 2 : 1;   // rows per loop step (even unit count)
+    static constexpr int USTEP = RSTEP * UPR;
+    static constexpr int DLOC = 64 * (NT - 1);        // largest local diagonal
+    static constexpr int NDIAG = NT + KC - 1;         // local diagonals per unit
+    static constexpr int SEQ_WORDS = M / 2;           // one reversed extension: 2M bytes
+    static constexpr int DSETS = 1;                   // one digit set: a barrier follows the accumulate
+    static constexpr size_t LDS_BYTES = 4 * (2 * (size_t)N + (size_t)DSETS * RV * 3 * SEQ_WORDS);
+    static constexpr int PLV = (M + 64) / 16;         // one key limb plane, in 16-byte units
+    static constexpr int QPW = M / 4 / WPC;           // coefficient quads per wavefront and half
+    static_assert(RV % RSTEP == 0 && USTEP % 2 == 0, "unit sequence must alternate evenly");
+};
+
+// Four consecutive coefficients 4q..4q+3 of rot_beta(src) in R_M:
+// rot_beta(p)[m] = p[(m + beta) mod M], negated when (m + beta) mod 2M >= M.
+template <int M>
+__device__ __attribute__((always_inline)) inline void kara_rot4(const uint4 *src, uint32_t q, uint32_t beta,
+                                                                 uint32_t (&rot)[4])
+{
+    const uint32_t rho = beta & 3, qa0 = beta >> 2;
+    const uint32_t Qa = (q + qa0) & (M / 2 - 1), Qb = (Qa + 1) & (M / 2 - 1);
+    const uint4 A4 = src[Qa & (M / 4 - 1)], B4 = src[Qb & (M / 4 - 1)];
+    const uint32_t sa = (Qa & (M / 4)) ? 0xFFFFFFFFu : 0u;
+    const uint32_t sb = (Qb & (M / 4)) ? 0xFFFFFFFFu : 0u;
+    const uint32_t w[8] = {(A4.x ^ sa) - sa, (A4.y ^ sa) - sa, (A4.z ^ sa) - sa, (A4.w ^ sa) - sa,
+                           (B4.x ^ sb) - sb, (B4.y ^ sb) - sb, (B4.z ^ sb) - sb, (B4.w ^ sb) - sb};
+    switch (rho) {  // wave-uniform
+    case 0: rot[0] = w[0]; rot[1] = w[1]; rot[2] = w[2]; rot[3] = w[3]; break;
+    case 1: rot[0] = w[1]; rot[1] = w[2]; rot[2] = w[3]; rot[3] = w[4]; break;
+    case 2: rot[0] = w[2]; rot[1] = w[3]; rot[2] = w[4]; rot[3] = w[5]; break;
+    default: rot[0] = w[3]; rot[1] = w[4]; rot[2] = w[5]; rot[3] = w[6]; break;
+    }
+}
+
+template <int N, int ELL, int CH>
+__global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g,
+                                                    const uint32_t *__restrict__ ctN,
+                                                    uint32_t accs_per_ct, int n,
+                                                    const v4i *__restrict__ bfrag,
+                                                    const uint32_t *__restrict__ corr, int log2B)
+{
+    using G = BrKara<N, ELL, CH>;
+    constexpr int M = G::M;
+    extern __shared__ uint8_t smem[];
+    uint32_t *accL = (uint32_t *)smem;  // [2][N]: per component, even half then odd half
+    uint32_t *digL = accL + 2 * N;      // [DSETS][RV][3 products][SEQ_WORDS]
+    auto seq = [&](int set, int r, int p) { return digL + ((set * G::RV + r) * 3 + p) * G::SEQ_WORDS; };
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int jc = wv / G::WPC;  // output component of this wavefront
+    const int hw = wv % G::WPC;  // its half of the tiles / coefficients
+    const uint32_t a_idx = blockIdx.x;
+    uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
+    for (int x = threadIdx.x; x < 2 * N; x += 64 * G::WAVES) {
+        const int m = x & (N - 1);
+        accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)] = row[x];
+    }
+    const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
+    const uint32_t drop = 32 - ELL * log2B;
+
+    const int ri = lane & 15, g = lane >> 4;
+    const int sh = (3 - ri) & 3;
+    const int S0 = M - 1 - ri + 16 * g;
+    const int limb = lane & 3, ss = (lane >> 2) & 3;
+    const int lane_v = (lane & 3) * G::PLV + (lane >> 4) + ((lane >> 2) & 3);
+    auto frag = [&](int i, int r, int p, int c) {
+        return bfrag + ((((size_t)i * G::RV + r) * 3 + p) * 2 + jc) * 4 * G::PLV + lane_v + c * G::KC * 4;
+    };
+    auto next_live = [&](int i) {
+        int k = i + 1;
+        while (k < n && __builtin_amdgcn_readfirstlane(crow[k]) == 0) ++k;
+        return k;
+    };
+
+    int i = next_live(-1);
+    v4i B0[G::KC], B1[G::KC];
+    {
+        const v4i *bp = frag(i < n ? i : 0, 0, 0, 0);
+#pragma unroll
+        for (int kb = 0; kb < G::KC; ++kb) B0[kb] = bp[kb * 4];
+    }
+    int set = 0;
+    __syncthreads();
+    while (i < n) {
+        const uint32_t a = __builtin_amdgcn_readfirstlane(crow[i]);
+        const int inext = next_live(i);
+
+        // digits of (X^{-a} acc_j - acc_j) for both halves; per digit row the
+        // sequences V_e, V_o and V_e + V_o, each as a reversed negacyclic
+        // extension of size M (bytes in memory order: coefficient 4q+3 first).
+        {
+            const uint32_t al = a >> 1, odd_a = a & 1;
+            const uint32_t *accJ = accL + jc * N;
+            const uint4 *srcE = (const uint4 *)(accJ + (odd_a ? M : 0));
+            const uint4 *srcO = (const uint4 *)(accJ + (odd_a ? 0 : M));
+            const uint4 *ownE = (const uint4 *)accJ, *ownO = (const uint4 *)(accJ + M);
+#pragma unroll
+            for (int qq = 0; qq < (G::QPW + 63) / 64; ++qq) {
+                if (G::QPW % 64 != 0 && qq * 64 + lane >= G::QPW) break;
+                const uint32_t q = hw * G::QPW + qq * 64 + lane;
+                uint32_t rE[4], rO[4];
+                kara_rot4<M>(srcE, q, al, rE);
+                kara_rot4<M>(srcO, q, al + odd_a, rO);
+                const uint4 E4 = ownE[q], O4 = ownO[q];
+                const uint32_t oE[4] = {E4.x, E4.y, E4.z, E4.w}, oO[4] = {O4.x, O4.y, O4.z, O4.w};
+                uint32_t tE[4], tO[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t dE = rE[u] - oE[u], dO = rO[u] - oO[u];
+                    tE[u] = drop ? (dE + (1u << (drop - 1))) >> drop : dE;
+                    tO[u] = drop ? (dO + (1u << (drop - 1))) >> drop : dO;
+                }
+#pragma unroll
+                for (int jj = 0; jj < ELL; ++jj) {
+#pragma unroll
+                    for (int h = 0; h < CH; ++h) {
+                        const uint32_t off = log2B * jj + 7 * h;
+                        const bool full = 7 * (h + 1) <= log2B;
+                        const uint32_t wdt = full ? 7u : (uint32_t)log2B - 7 * h;
+                        // byte constants: offsets (64, 63) for 7-bit digits, none otherwise
+                        const uint32_t oe = full ? 64u : 0u, oo = full ? 63u : 0u;
+                        const uint32_t cE = (128u - oe) * 0x01010101u, nE = (128u + oe) * 0x01010101u;
+                        const uint32_t cO = (128u - oo) * 0x01010101u, nO = (128u + oo) * 0x01010101u;
+                        const uint32_t cS = (128u - oe - oo) * 0x01010101u, nS = (128u + oe + oo) * 0x01010101u;
+                        uint32_t pe = __builtin_amdgcn_ubfe(tE[3], off, wdt);
+                        pe |= __builtin_amdgcn_ubfe(tE[2], off, wdt) << 8;
+                        pe |= __builtin_amdgcn_ubfe(tE[1], off, wdt) << 16;
+                        pe |= __builtin_amdgcn_ubfe(tE[0], off, wdt) << 24;
+                        uint32_t po = __builtin_amdgcn_ubfe(tO[3], off, wdt);
+                        po |= __builtin_amdgcn_ubfe(tO[2], off, wdt) << 8;
+                        po |= __builtin_amdgcn_ubfe(tO[1], off, wdt) << 16;
+                        po |= __builtin_amdgcn_ubfe(tO[0], off, wdt) << 24;
+                        const uint32_t ps = pe + po;  // bytes <= 254, no carries
+                        // bytewise x - o and o - x: (x + 128 - o) ^ 0x80, (128 + o - x) ^ 0x80
+                        const int r = jc * G::RPC + jj * CH + h;
+                        uint32_t *sE = seq(set, r, 0), *sO = seq(set, r, 1), *sS = seq(set, r, 2);
+                        sE[M / 4 - q - 1] = (pe + cE) ^ 0x80808080u;
+                        sE[M / 2 - q - 1] = (nE - pe) ^ 0x80808080u;
+                        sO[M / 4 - q - 1] = (po + cO) ^ 0x80808080u;
+                        sO[M / 2 - q - 1] = (nO - po) ^ 0x80808080u;
+                        sS[M / 4 - q - 1] = (ps + cS) ^ 0x80808080u;
+                        sS[M / 2 - q - 1] = (nS - ps) ^ 0x80808080u;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        // the offset correction of this step, for the coefficients this lane accumulates
+        uint32_t wE[G::NT], wO[G::NT];
+        {
+            const uint32_t *cp = corr + ((size_t)i * 2 + jc) * N;
+#pragma unroll
+            for (int t = 0; t < G::NT; ++t) {
+                const int m = 64 * (hw * G::NT + t) + 16 * ss + 4 * g + limb;
+                wE[t] = cp[m];
+                wO[t] = cp[M + m];
+            }
+        }
+
+        v4i C[3][G::NT];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int t = 0; t < G::NT; ++t) C[p][t] = v4i{0, 0, 0, 0};
+
+        auto one_unit = [&](const int r, auto P_, const int c, v4i(&Bc)[G::KC], v4i(&Bn)[G::KC],
+                            const v4i *np) {
+            constexpr int p = decltype(P_)::value;
+#pragma unroll
+            for (int kb = 0; kb < G::KC; ++kb) Bn[kb] = np[kb * 4];
+            __builtin_amdgcn_sched_barrier(0);
+            const int dshift = 64 * (hw * G::NT - c * G::KC);
+            const uint32_t *ab = seq(set, r, p) + (S0 - dshift - sh - G::DLOC) / 4;
+            v4i Af[2];
+            uint32_t wn[5];
+            auto read_words = [&](const int dd, uint32_t(&w)[5]) {
+                const uint32_t *wp = ab + 16 * dd;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) w[k] = wp[k];
+            };
+            auto align = [&](const uint32_t(&w)[5], v4i &A) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) A[k] = (int)__builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+            };
+            read_words(0, wn);
+            align(wn, Af[0]);
+#pragma unroll
+            for (int dd = 0; dd < G::NDIAG; ++dd) {
+                const int dl = G::DLOC - 64 * dd;
+                if (dd + 1 < G::NDIAG) read_words(dd + 1, wn);
+#pragma unroll
+                for (int kb = 0; kb < G::KC; ++kb) {
+                    const int m0 = dl + 64 * kb;
+                    if (m0 >= 0 && m0 <= 64 * (G::NT - 1))
+                        C[p][m0 / 64] =
+                            __builtin_amdgcn_mfma_i32_16x16x64_i8(Af[dd & 1], Bc[kb], C[p][m0 / 64], 0, 0, 0);
+                }
+                if (dd + 1 < G::NDIAG) align(wn, Af[(dd + 1) & 1]);
+            }
+        };
+
+#pragma unroll 1
+        for (int r = 0; r < G::RV; r += G::RSTEP) {
+            StaticFor<0, G::USTEP>::run([&](auto U_) {
+                constexpr int u = decltype(U_)::value;
+                constexpr int rr = u / G::UPR, p = (u % G::UPR) / G::NCH, c = u % G::NCH;
+                const v4i *np;
+                if constexpr (u + 1 < G::USTEP) {
+                    constexpr int u2 = u + 1;
+                    np = frag(i, r + u2 / G::UPR, (u2 % G::UPR) / G::NCH, u2 % G::NCH);
+                } else {
+                    np = (r + G::RSTEP < G::RV) ? frag(i, r + G::RSTEP, 0, 0)
+                                                : frag(inext < n ? inext : i, 0, 0, 0);
+                }
+                if constexpr (u % 2 == 0) one_unit(r + rr, IC<p>{}, c, B0, B1, np);
+                else one_unit(r + rr, IC<p>{}, c, B1, B0, np);
+            });
+        }
+
+        // limbs -> uint32 (mod 2^32) by a reduce-scatter over the lane quad:
+        // lane with limb l ends with the full sum of row v = l of the tile.
+        const bool p1 = lane & 1, h1 = lane & 2;
+        auto rs = [&](const uint32_t (&z)[4]) -> uint32_t {
+            const uint32_t y0 = z[0] << (8 * limb), y1 = z[1] << (8 * limb);
+            const uint32_t y2 = z[2] << (8 * limb), y3 = z[3] << (8 * limb);
+            const uint32_t za = (p1 ? y1 : y0) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(p1 ? y0 : y1), 0xB1, 0xF, 0xF, false);
+            const uint32_t zb = (p1 ? y3 : y2) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(p1 ? y2 : y3), 0xB1, 0xF, 0xF, false);
+            return (h1 ? zb : za) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(h1 ? za : zb), 0x4E, 0xF, 0xF, false);
+        };
+        uint32_t *accE = accL + jc * N, *accO = accE + M;
+#pragma unroll
+        for (int t = 0; t < G::NT; ++t) {
+            const int m = 64 * (hw * G::NT + t) + 16 * ss + 4 * g + limb;
+            uint32_t zo[4], z1[4], z2[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                z1[v] = (uint32_t)C[0][t][v];
+                z2[v] = (uint32_t)C[1][t][v];
+                zo[v] = (uint32_t)C[2][t][v] - z1[v] - z2[v];
+            }
+            atomicAdd(&accO[m], rs(zo) + wO[t]);          // (a b)_o = P_s - P_e - P_o
+            atomicAdd(&accE[m], rs(z1) + wE[t]);          // (a b)_e = P_e + Y P_o
+            const uint32_t x2 = rs(z2);
+            if (m + 1 < M) atomicAdd(&accE[m + 1], x2);
+            else atomicAdd(&accE[0], 0u - x2);
+        }
+        __syncthreads();  // the next digits overwrite the set all wavefronts have just read
+        if (G::DSETS > 1) set ^= 1;
+        i = inext;
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < 2 * N; x += 64 * G::WAVES) {
+        const int m = x & (N - 1);
+        row[x] = accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static int ilog2i(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
@@ -737,6 +1038,24 @@ static hipError_t launch_br_mfma_t(const Geometry &G, uint32_t *acc, const uint3
     X(2048, 2, 2)             \
     X(2048, 4, 1)
 
+template <int N, int ELL, int CH>
+static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
+                                   uint32_t accs_per_ct, const void *brk_frag, const uint32_t *corr,
+                                   hipStream_t s)
+{
+    using GK = BrKara<N, ELL, CH>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_br_kara<N, ELL, CH>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)GK::LDS_BYTES);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_br_kara<N, ELL, CH>), dim3(A), dim3(64 * GK::WAVES), GK::LDS_BYTES, s, acc, ctN,
+                       accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+    return hipGetLastError();
+}
+
 bool br_mfma_supported(const Geometry &G)
 {
     const int ch = digit_chunks(G.g_log2B);
@@ -753,6 +1072,19 @@ hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN,
     const int ch = digit_chunks(G.g_log2B);
 #define X(n_, l_, c_) \
     if (G.N == n_ && G.g_ell == l_ && ch == c_) return launch_br_mfma_t<n_, l_, c_>(G, acc, ctN, A, accs_per_ct, brk_frag, s);
+    FDFB_BR_MFMA_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_br_kara(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
+                          uint32_t accs_per_ct, const void *brk_frag, const uint32_t *corr, hipStream_t s)
+{
+    if (!A) return hipSuccess;
+    const int ch = digit_chunks(G.g_log2B);
+#define X(n_, l_, c_) \
+    if (G.N == n_ && G.g_ell == l_ && ch == c_) \
+        return launch_br_kara_t<n_, l_, c_>(G, acc, ctN, A, accs_per_ct, brk_frag, corr, s);
     FDFB_BR_MFMA_CASES(X)
 #undef X
     return hipErrorInvalidValue;
