@@ -304,33 +304,42 @@ std::vector<int8_t> build_ks_fragments(const uint32_t *key, uint32_t din, uint32
     return out;
 }
 
-// Key operand of the Karatsuba blind rotation: block (i, r', p, j) holds 4
-// byte planes of M + 64 bytes (M = N/2) for the half-ring key polynomial of
-// product p: K_e[x] = K[2x], K_o[x] = K[2x+1] or K_e + K_o, negacyclically
-// extended in Z[Y]/(Y^M + 1), times 2^(7h) for digit chunk h.
+// Key operand of the Karatsuba blind rotation, in the lane order of the MFMA
+// B operand: block (i, r', p, j, kb) holds for lane L and byte t limb L % 4 of
+// K'~[64 kb + 16 (L / 16) + (L / 4 % 4) + t], where K' is the half-ring key
+// polynomial of product p (K_e[x] = K[2x], K_o[x] = K[2x+1], or K_e + K_o)
+// times 2^(7h) for digit chunk h, and K'~ its negacyclic extension in
+// Z[Y]/(Y^M + 1), M = N/2.
 std::vector<int8_t> build_brk_kara(const fdfb_ctx &c)
 {
     const fdfb_params &P = c.P;
     const uint32_t N = P.N, M = N / 2, ell = P.g_ell, CH = fdfbk::digit_chunks(P.g_log2B);
-    const uint32_t RPC = ell * CH, RV = 2 * RPC, R = 2 * ell, PL = M + 64;
-    std::vector<int8_t> out((size_t)P.n * RV * 3 * 2 * 4 * PL);
+    const uint32_t RPC = ell * CH, RV = 2 * RPC, R = 2 * ell, NKB = M / 64;
+    std::vector<int8_t> out((size_t)P.n * RV * 3 * 2 * NKB * 1024);
     parallel_for((size_t)P.n * RV, [&](size_t id) {
         const uint32_t i = id / RV, rv = id % RV;
         const uint32_t comp_in = rv / RPC, rr = rv % RPC, jd = rr / CH, h = rr % CH;
         const uint32_t row = comp_in * ell + jd;
+        std::vector<uint32_t> ext(M + 64);
         for (uint32_t j = 0; j < 2; ++j) {
             const uint32_t *K = &c.brk[(((size_t)i * R + row) * 2 + j) * N];
             for (uint32_t p = 0; p < 3; ++p) {
-                int8_t *dst = &out[((id * 3 + p) * 2 + j) * 4 * PL];
-                for (uint32_t x = 0; x < PL; ++x) {  // PL <= 2M
+                for (uint32_t x = 0; x < M + 64; ++x) {  // M + 64 <= 2M
                     const uint32_t xx = x < M ? x : x - M;
                     uint32_t w = p == 0 ? K[2 * xx] : p == 1 ? K[2 * xx + 1] : K[2 * xx] + K[2 * xx + 1];
                     if (x >= M) w = 0u - w;
-                    w <<= 7 * h;
-                    int8_t limbs[4];
-                    balanced_limbs(w, limbs);
-                    for (uint32_t l = 0; l < 4; ++l) dst[l * PL + x] = limbs[l];
+                    ext[x] = w << (7 * h);
                 }
+                int8_t *dst = &out[((id * 3 + p) * 2 + j) * NKB * 1024];
+                for (uint32_t kb = 0; kb < NKB; ++kb)
+                    for (uint32_t L = 0; L < 64; ++L) {
+                        const uint32_t sft = (L >> 2) & 3, l = L & 3, gg = L >> 4;
+                        for (uint32_t t = 0; t < 16; ++t) {
+                            int8_t limbs[4];
+                            balanced_limbs(ext[64 * kb + 16 * gg + sft + t], limbs);
+                            dst[(kb * 64 + L) * 16 + t] = limbs[l];
+                        }
+                    }
             }
         }
     });

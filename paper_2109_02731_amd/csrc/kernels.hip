@@ -619,9 +619,13 @@ __global__ __launch_bounds__(256, 2) void k_br_mfma(uint32_t *__restrict__ acc_g
 // accumulate in three register sets over all digit rows; the accumulator
 // is kept in LDS in even/odd order, where X^(-a) acts on each half as a
 // negacyclic rotation of size M (and swaps the halves for odd a).
-// Everything else (Toeplitz A fragments per diagonal, 4 key shifts x 4
-// limbs as the 16 B columns, planar key limbs, unit double buffering) is
-// as in k_br_mfma, at size M.
+// Each product is the Toeplitz GEMM of k_br_mfma at size M (A fragments
+// built once per diagonal, 16 B columns = 4 key shifts x 4 balanced limbs,
+// units of 8 k-blocks with the next unit's B fragments in flight), with one
+// change of tiling: output row i of a tile at m0 is coefficient
+// m0 - 1 + 4i + s for key shift s in {0, 1, 2, 3}, which makes every lane's
+// 16 A bytes start on a dword (four LDS words, no byte alignment) and puts
+// the shifts in the lane-ordered B fragments built on the host.
 // ---------------------------------------------------------------------------
 template <int V> struct IC { static constexpr int value = V; };
 template <int I, int END> struct StaticFor {
@@ -654,7 +658,6 @@ struct BrKara {
     static constexpr int SEQ_WORDS = M / 2;           // one reversed extension: 2M bytes
     static constexpr int DSETS = 1;                   // one digit set: a barrier follows the accumulate
     static constexpr size_t LDS_BYTES = 4 * (2 * (size_t)N + (size_t)DSETS * RV * 3 * SEQ_WORDS);
-    static constexpr int PLV = (M + 64) / 16;         // one key limb plane, in 16-byte units
     static constexpr int QPW = M / 4 / WPC;           // coefficient quads per wavefront and half
     static_assert(RV % RSTEP == 0 && USTEP % 2 == 0, "unit sequence must alternate evenly");
 };
@@ -707,13 +710,15 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
     const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
     const uint32_t drop = 32 - ELL * log2B;
 
+    // Output row i of a tile starting at m0, for key shift s, is coefficient
+    // m0 - 1 + 4 i + s, so lane (i, g) of the A fragment on diagonal d reads
+    // bytes Rv[M - d - 4i + 16g ..+15] of the reversed extension
+    // Rv[z] = V~[M - 1 - z]: four dword-aligned LDS words, no byte shifts.
     const int ri = lane & 15, g = lane >> 4;
-    const int sh = (3 - ri) & 3;
-    const int S0 = M - 1 - ri + 16 * g;
+    const int S0 = M - 4 * ri + 16 * g;
     const int limb = lane & 3, ss = (lane >> 2) & 3;
-    const int lane_v = (lane & 3) * G::PLV + (lane >> 4) + ((lane >> 2) & 3);
     auto frag = [&](int i, int r, int p, int c) {
-        return bfrag + ((((size_t)i * G::RV + r) * 3 + p) * 2 + jc) * 4 * G::PLV + lane_v + c * G::KC * 4;
+        return bfrag + (((((size_t)i * G::RV + r) * 3 + p) * 2 + jc) * G::NKB + c * G::KC) * 64 + lane;
     };
     auto next_live = [&](int i) {
         int k = i + 1;
@@ -726,7 +731,7 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
     {
         const v4i *bp = frag(i < n ? i : 0, 0, 0, 0);
 #pragma unroll
-        for (int kb = 0; kb < G::KC; ++kb) B0[kb] = bp[kb * 4];
+        for (int kb = 0; kb < G::KC; ++kb) B0[kb] = bp[kb * 64];
     }
     int set = 0;
     __syncthreads();
@@ -801,7 +806,7 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
             const uint32_t *cp = corr + ((size_t)i * 2 + jc) * N;
 #pragma unroll
             for (int t = 0; t < G::NT; ++t) {
-                const int m = 64 * (hw * G::NT + t) + 16 * ss + 4 * g + limb;
+                const int m = (64 * (hw * G::NT + t) + 16 * g + 4 * limb + ss - 1) & (M - 1);
                 wE[t] = cp[m];
                 wO[t] = cp[M + m];
             }
@@ -817,27 +822,22 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
                             const v4i *np) {
             constexpr int p = decltype(P_)::value;
 #pragma unroll
-            for (int kb = 0; kb < G::KC; ++kb) Bn[kb] = np[kb * 4];
+            for (int kb = 0; kb < G::KC; ++kb) Bn[kb] = np[kb * 64];
             __builtin_amdgcn_sched_barrier(0);
+            // local diagonal dl = 64 (t - kb) is global d = dl + dshift
             const int dshift = 64 * (hw * G::NT - c * G::KC);
-            const uint32_t *ab = seq(set, r, p) + (S0 - dshift - sh - G::DLOC) / 4;
+            // dword-aligned, not 16-byte aligned: read as four dwords
+            const uint32_t *ab = seq(set, r, p) + (S0 - dshift - G::DLOC) / 4;
+            auto afrag = [&](const int dd, v4i &A) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) A[k] = (int)ab[16 * dd + k];
+            };
             v4i Af[2];
-            uint32_t wn[5];
-            auto read_words = [&](const int dd, uint32_t(&w)[5]) {
-                const uint32_t *wp = ab + 16 * dd;
-#pragma unroll
-                for (int k = 0; k < 5; ++k) w[k] = wp[k];
-            };
-            auto align = [&](const uint32_t(&w)[5], v4i &A) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) A[k] = (int)__builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
-            };
-            read_words(0, wn);
-            align(wn, Af[0]);
+            afrag(0, Af[0]);
 #pragma unroll
             for (int dd = 0; dd < G::NDIAG; ++dd) {
                 const int dl = G::DLOC - 64 * dd;
-                if (dd + 1 < G::NDIAG) read_words(dd + 1, wn);
+                if (dd + 1 < G::NDIAG) afrag(dd + 1, Af[(dd + 1) & 1]);
 #pragma unroll
                 for (int kb = 0; kb < G::KC; ++kb) {
                     const int m0 = dl + 64 * kb;
@@ -845,7 +845,6 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
                         C[p][m0 / 64] =
                             __builtin_amdgcn_mfma_i32_16x16x64_i8(Af[dd & 1], Bc[kb], C[p][m0 / 64], 0, 0, 0);
                 }
-                if (dd + 1 < G::NDIAG) align(wn, Af[(dd + 1) & 1]);
             }
         };
 
@@ -877,10 +876,15 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
             const uint32_t zb = (p1 ? y3 : y2) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(p1 ? y2 : y3), 0xB1, 0xF, 0xF, false);
             return (h1 ? zb : za) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(h1 ? za : zb), 0x4E, 0xF, 0xF, false);
         };
+        // row v of lane (s, l, g) is coefficient 64 t + mb of the product, with
+        // mb = 16 g + 4 v + s - 1; after the reduce-scatter v = l.  Only
+        // coefficient -1 (tile 0 of the first half, mb = -1) wraps: it is
+        // -(coefficient M - 1).
+        const int mb = 16 * g + 4 * limb + ss - 1;
         uint32_t *accE = accL + jc * N, *accO = accE + M;
 #pragma unroll
         for (int t = 0; t < G::NT; ++t) {
-            const int m = 64 * (hw * G::NT + t) + 16 * ss + 4 * g + limb;
+            const int m = 64 * (hw * G::NT + t) + mb;
             uint32_t zo[4], z1[4], z2[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -888,11 +892,15 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
                 z2[v] = (uint32_t)C[1][t][v];
                 zo[v] = (uint32_t)C[2][t][v] - z1[v] - z2[v];
             }
-            atomicAdd(&accO[m], rs(zo) + wO[t]);          // (a b)_o = P_s - P_e - P_o
-            atomicAdd(&accE[m], rs(z1) + wE[t]);          // (a b)_e = P_e + Y P_o
-            const uint32_t x2 = rs(z2);
-            if (m + 1 < M) atomicAdd(&accE[m + 1], x2);
-            else atomicAdd(&accE[0], 0u - x2);
+            const uint32_t xo = rs(zo), x1 = rs(z1), x2 = rs(z2);
+            if (t == 0 && hw == 0 && mb < 0) {
+                atomicAdd(&accO[M - 1], wO[t] - xo);  // (a b)_o = P_s - P_e - P_o
+                atomicAdd(&accE[M - 1], wE[t] - x1);  // (a b)_e = P_e + Y P_o
+            } else {
+                atomicAdd(&accO[m], xo + wO[t]);
+                atomicAdd(&accE[m], x1 + wE[t]);
+            }
+            atomicAdd(&accE[m + 1], x2);  // m + 1 <= M - 1: no wrap
         }
         __syncthreads();  // the next digits overwrite the set all wavefronts have just read
         if (G::DSETS > 1) set ^= 1;
