@@ -57,7 +57,7 @@ def kernel_source_hash() -> str:
 def load_traffic(unit_count: float):
     """HBM bytes per launch of the blind-rotation kernel from committed
     counter data, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "br_mfma_traffic.json")
+    path = os.path.join(ROOT, "profiles", "br_kara_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
@@ -245,11 +245,18 @@ def main():
     ops = br_ops_per_accumulator(p) * units_per_step
     achieved = ops / (br_ms * 1e-3) / 1e12
     traffic = load_traffic(units_per_step)
-    roofline = {"bound": "mfma", "kernel": "k_br_mfma<1024,3,1>", "achieved": achieved,
+    executed = achieved * 0.75  # one Karatsuba level: 3 half-size products for 4
+    launches = ctx.br_launches(B * p.boot_ell, p.boot_ell) + ctx.br_launches(B, 1)
+    roofline = {"bound": "mfma", "kernel": "k_br_kara<1024,3,1>", "achieved": achieved,
                 "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_INT8_TOPS,
                 "traffic": traffic,
-                "ops_per_launch_avg": ops / 2, "avg_launch_ms": br_ms / 2,
-                "note": "int8 tera-ops/s; launches alternate 2048 and 1024 accumulators"}
+                "ops_per_launch_avg": ops / launches, "avg_launch_ms": br_ms / launches,
+                "launches_per_step": launches,
+                "executed_mfma_frac": executed / PEAK_INT8_TOPS,
+                "note": "int8 tera-ops/s of the schoolbook product work; the kernel issues 3/4 of it "
+                        "on MFMA (one Karatsuba level), executed_mfma_frac is that rate over the peak; "
+                        "the sign rotations (2048 accumulators) and the function rotation (1024) run in "
+                        "launches of the resident capacity"}
 
     serving = None
     if args.serving_requests > 0:

@@ -295,6 +295,15 @@ int fdfb_profile(fdfb_ctx *ctx, int enable);
  * number of calls in *calls, and forget the events. */
 int fdfb_profile_read(fdfb_ctx *ctx, double *ms, uint32_t *calls);
 
+/* Number of kernel launches one batched blind rotation of `accumulators`
+ * accumulators (`per_ct` consecutive ones per ciphertext, 1 <= per_ct)
+ * takes on the current device, for matching per-launch profiles: the MFMA
+ * form is issued in rounds of the device's resident workgroup capacity, the
+ * plain and direct forms in one launch.  0 accumulators take 0 launches.
+ * FDFB_EINVAL on a null pointer or per_ct = 0, FDFB_EDEVICE on a HIP error. */
+int fdfb_br_launches(fdfb_ctx *ctx, uint32_t accumulators, uint32_t per_ct, uint32_t flags,
+                     uint32_t *launches);
+
 /* Raise or clear the abort flag; while raised, device entry points return
  * FDFB_EABORTED without enqueuing work. */
 void fdfb_set_abort(fdfb_ctx *ctx, int raised);

@@ -59,7 +59,7 @@ EXPORTED = [
     "fdfb_keyswitch", "fdfb_modswitch", "fdfb_blind_rotate", "fdfb_sample_extract",
     "fdfb_packing_keyswitch", "fdfb_pubmux", "fdfb_encrypt_debug", "fdfb_decrypt_debug",
     "fdfb_export_keys", "fdfb_import_keys", "fdfb_get_key", "fdfb_profile", "fdfb_profile_read",
-    "fdfb_set_abort", "fdfb_free", "fdfb_last_error",
+    "fdfb_br_launches", "fdfb_set_abort", "fdfb_free", "fdfb_last_error",
     "fdfb_server_create", "fdfb_server_submit", "fdfb_server_poll", "fdfb_server_wait",
     "fdfb_server_stats", "fdfb_server_destroy", "fdfb_affine",
 ]
@@ -96,6 +96,7 @@ def lib():
             "fdfb_profile": (i, [P, i]),
             "fdfb_profile_read": (i, [P, P, P]),
             "fdfb_set_abort": (None, [P, i]),
+            "fdfb_br_launches": (i, [P, u32, u32, u32, P]),
             "fdfb_free": (None, [P]),
             "fdfb_last_error": (C.c_char_p, []),
             "fdfb_server_create": (i, [P, u32, u32, sz, u32, P]),
@@ -223,6 +224,12 @@ class Context:
         calls = C.c_uint32()
         _check(lib().fdfb_profile_read(self._h, ms, C.byref(calls)))
         return dict(zip(PHASES, list(ms))), calls.value
+
+    def br_launches(self, accumulators: int, per_ct: int = 1, flags: int = 0) -> int:
+        """Kernel launches of one batched blind rotation of this many accumulators."""
+        n = C.c_uint32()
+        _check(lib().fdfb_br_launches(self._h, accumulators, per_ct, flags, C.byref(n)))
+        return n.value
 
     def set_abort(self, raised: bool):
         lib().fdfb_set_abort(self._h, 1 if raised else 0)

@@ -873,6 +873,19 @@ int fdfb_profile_read(fdfb_ctx *c, double *ms, uint32_t *calls)
     return rc;
 }
 
+int fdfb_br_launches(fdfb_ctx *c, uint32_t A, uint32_t per_ct, uint32_t flags, uint32_t *launches)
+{
+    if (!c || !launches) return fail(FDFB_EINVAL, "null argument");
+    if (per_ct == 0) return fail(FDFB_EINVAL, "per_ct must be at least 1");
+    int rc = check_form(*c, flags);
+    if (rc) return rc;
+    if ((rc = ensure_device(*c))) return rc;
+    *launches = A ? 1 : 0;
+    if (A && !(flags & FDFB_PLAIN) && c->mfma_ok && c->kara)
+        K_TRY(fdfbk::br_kara_launches(c->geom, A, per_ct, launches));
+    return FDFB_OK;
+}
+
 void fdfb_set_abort(fdfb_ctx *c, int raised)
 {
     if (c) c->abort_flag.store(raised ? 1 : 0);

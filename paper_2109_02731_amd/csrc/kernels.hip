@@ -9,6 +9,7 @@
 //  * k_br_plain -- one accumulator per workgroup, uint32 multiply-add on the
 //    vector ALUs (the comparison form).
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <stdint.h>
 
 #include "kernels.h"
@@ -1046,6 +1047,28 @@ static hipError_t launch_br_mfma_t(const Geometry &G, uint32_t *acc, const uint3
     X(2048, 2, 2)             \
     X(2048, 4, 1)
 
+// Workgroups of k_br_kara resident on the whole device at once.
+template <int N, int ELL, int CH>
+static hipError_t br_kara_capacity(uint32_t *cap_out)
+{
+    using GK = BrKara<N, ELL, CH>;
+    static uint32_t cap = 0;
+    if (!cap) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_br_kara<N, ELL, CH>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)GK::LDS_BYTES);
+        int dev = 0, cus = 0, per_cu = 0;
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_br_kara<N, ELL, CH>,
+                                                             64 * GK::WAVES, GK::LDS_BYTES);
+        if (e != hipSuccess) return e;
+        cap = (uint32_t)std::max(1, per_cu * cus);
+    }
+    *cap_out = cap;
+    return hipSuccess;
+}
+
 template <int N, int ELL, int CH>
 static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
                                    uint32_t accs_per_ct, const void *brk_frag, const uint32_t *corr,
@@ -1059,9 +1082,23 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_br_kara<N, ELL, CH>), dim3(A), dim3(64 * GK::WAVES), GK::LDS_BYTES, s, acc, ctN,
-                       accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
-    return hipGetLastError();
+    // Launch in rounds of the resident capacity (whole ciphertexts): the
+    // workgroups of one launch start together and walk the key in step, so a
+    // key block is fetched into each XCD's L2 once and shared, where a second
+    // round started by completions would drift and re-fetch.
+    uint32_t cap = 0;
+    hipError_t e0 = br_kara_capacity<N, ELL, CH>(&cap);
+    if (e0 != hipSuccess) return e0;
+    const uint32_t chunk = std::max(accs_per_ct, cap / accs_per_ct * accs_per_ct);
+    for (uint32_t a0 = 0; a0 < A; a0 += chunk) {
+        const uint32_t cnt = std::min(chunk, A - a0);
+        hipLaunchKernelGGL((k_br_kara<N, ELL, CH>), dim3(cnt), dim3(64 * GK::WAVES), GK::LDS_BYTES, s,
+                           acc + (size_t)a0 * 2 * N, ctN + (size_t)(a0 / accs_per_ct) * (G.n + 1), accs_per_ct,
+                           G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 bool br_mfma_supported(const Geometry &G)
@@ -1083,6 +1120,23 @@ hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN,
     FDFB_BR_MFMA_CASES(X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+hipError_t br_kara_launches(const Geometry &G, uint32_t A, uint32_t accs_per_ct, uint32_t *launches)
+{
+    *launches = 0;
+    if (!A) return hipSuccess;
+    const int ch = digit_chunks(G.g_log2B);
+    uint32_t cap = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define X(n_, l_, c_) \
+    if (G.N == n_ && G.g_ell == l_ && ch == c_) e = br_kara_capacity<n_, l_, c_>(&cap);
+    FDFB_BR_MFMA_CASES(X)
+#undef X
+    if (e != hipSuccess) return e;
+    const uint32_t chunk = std::max(accs_per_ct, cap / accs_per_ct * accs_per_ct);
+    *launches = (A + chunk - 1) / chunk;
+    return hipSuccess;
 }
 
 hipError_t launch_br_kara(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,

@@ -322,3 +322,17 @@ def test_fdfb_n2048_vs_oracle(keys_2048):
     refs = run_oracle_many(lambda k: oracle.fdfb(ok, r0, r1, cts[k]), len(msgs))
     for k in range(len(msgs)):
         assert np.array_equal(out[k], refs[k]), k
+
+
+def test_br_launch_count(c2):
+    """The batched form runs in rounds of the resident capacity (whole
+    ciphertexts); the plain form in one launch; nothing for no accumulators."""
+    ctx = c2[0]
+    assert ctx.br_launches(0, 2) == 0
+    one = ctx.br_launches(2, 2)
+    assert one == 1
+    many = ctx.br_launches(1 << 16, 2)
+    assert many >= 2
+    assert ctx.br_launches(1 << 16, 2, flags=fd.PLAIN) == 1
+    with pytest.raises(fd.FdfbError):
+        ctx.br_launches(4, 0)
