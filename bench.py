@@ -153,6 +153,60 @@ def serving_bench(fd, torch, W, ctx2, count):
     return {"saturated": sat, "sustainable": sus}
 
 
+def mixed_bench(fd, torch, W, ctx2, steps: int):
+    """Uneven batch over two ring degrees (2048 samples at n=630 N=1024 and
+    2048 at n=750 N=2048, 64 tables per half, Zipf(1.2) ids): one
+    fdfb_bootstrap_multi submission vs the two jobs one after the other."""
+    halves = [("C2", W.C2, ctx2), ("C3B", W.C3B, None)]
+    jobs = []
+    for name, p, c in halves:
+        c = c or fd.Context.keygen(p, W.KEY_SEED[name])
+        lids = np.array([c.register_lut(W.random_lut(W.LUT_SEED[name] * 100 + j, p.t)) for j in range(64)],
+                        dtype=np.int32)
+        which = W.zipf_indices(W.LUT_SEED[name], 2048, 64, 1.2)
+        cts = fd.to_device(c.encrypt_debug(W.messages(W.MSG_SEED[name], 2048, p.t), seed=W.MSG_SEED[name]))
+        ids = torch.from_numpy(lids[which]).cuda()
+        out = torch.empty((2048, p.n + 1), dtype=torch.int32, device="cuda")
+        jobs.append((c, cts, ids, out, 0))
+
+    def run(multi: bool) -> float:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            if multi:
+                fd.bootstrap_multi(jobs)
+            else:
+                for c, cts, ids, out, fl in jobs:
+                    c.bootstrap_batch(cts, ids, out, fl)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    run(True)
+    t_multi, t_seq = run(True), run(False)
+    return {"workload": "2048 samples n=630 N=1024 t=16 + 2048 samples n=750 N=2048 t=32, "
+                        "64 tables per half, Zipf(1.2) ids",
+            "bootstraps_per_s": 4096 / t_multi, "ms_per_submission": t_multi * 1e3,
+            "ms_jobs_in_sequence": t_seq * 1e3, "steps": steps}
+
+
+def multi_lut_bench(fd, torch, W, ctx, p, d_cts, B: int, L: int, steps: int, single_ms: float):
+    """L tables per sample on the bench batch: the sign rotations are shared,
+    so one call does ell_boot + L blind rotations per sample."""
+    lids = np.array([ctx.register_lut(W.random_lut(W.LUT_SEED["C2"] * 10 + l, p.t)) for l in range(L)],
+                    dtype=np.int32)
+    ids = torch.from_numpy(np.tile(lids, (B, 1))).cuda()
+    out = torch.empty((B, L, p.n + 1), dtype=torch.int32, device="cuda")
+    ctx.bootstrap_multi_lut(d_cts, ids, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.bootstrap_multi_lut(d_cts, ids, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"tables_per_sample": L, "table_evaluations_per_s": B * L / dt, "ms_per_call": dt * 1e3,
+            "speedup_vs_single_table_calls": L * single_ms / (dt * 1e3), "steps": steps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +217,10 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--serving-requests", type=int, default=300,
                     help="requests per serving run (0 skips the serving measurement)")
+    ap.add_argument("--multi-lut", type=int, default=4, metavar="L",
+                    help="also time L tables per sample on the bench batch (0 skips)")
+    ap.add_argument("--mixed-steps", type=int, default=0,
+                    help="also time the uneven two-degree batch (one multi-job submission) this many times")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -258,6 +316,16 @@ def main():
                         "the sign rotations (2048 accumulators) and the function rotation (1024) run in "
                         "launches of the resident capacity"}
 
+    multi_lut = None
+    if args.multi_lut > 0:
+        print(f"[bench] {args.multi_lut} tables per sample", file=sys.stderr, flush=True)
+        multi_lut = multi_lut_bench(fd, torch, W, ctx, p, d_cts, B, args.multi_lut, 3, wall / K * 1e3)
+
+    mixed = None
+    if args.mixed_steps > 0:
+        print("[bench] uneven two-degree batch", file=sys.stderr, flush=True)
+        mixed = mixed_bench(fd, torch, W, ctx, args.mixed_steps)
+
     serving = None
     if args.serving_requests > 0:
         print(f"[bench] serving: {args.serving_requests} requests per run", file=sys.stderr, flush=True)
@@ -293,6 +361,8 @@ def main():
         "phases_ms_per_step": {k: v / calls for k, v in phases.items()},
         "roofline": roofline,
         "serving": serving,
+        "multi_lut": multi_lut,
+        "mixed": mixed,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -118,6 +118,24 @@ int fdfb_register_lut(fdfb_ctx *ctx, const uint32_t *table, int32_t *lut_id);
 int fdfb_bootstrap_batch(fdfb_ctx *ctx, const uint32_t *d_cts, const int32_t *d_lut_ids,
                          uint32_t B, uint32_t *d_out, uint32_t flags, void *stream);
 
+/*
+ * Several functions of one input (Sec. "Application of Functional
+ * Bootstrapping", multiple univariate functions with the same input: the
+ * sign accumulators depend on the input only, so they are computed once and
+ * reused by every table):
+ * for each sample, ell_boot sign blind rotations, then per table a public
+ * mux and a function blind rotation.  ell_boot + L blind rotations per
+ * sample instead of L (ell_boot + 1).
+ *   d_lut_ids  int32 [B][L], table l of sample b at b L + l
+ *   d_out      uint32 [B][L][n+1] (or [B][L][N+1] with FDFB_OUT_EXTRACTED);
+ *              output (b, l) is bit-identical to fdfb_bootstrap_batch of
+ *              sample b with table d_lut_ids[b L + l]
+ * L = 0 is FDFB_EINVAL; B = 0 is a no-op.  Scratch grows with B L.  Other
+ * arguments and errors as fdfb_bootstrap_batch.
+ */
+int fdfb_bootstrap_multi_lut(fdfb_ctx *ctx, const uint32_t *d_cts, const int32_t *d_lut_ids, uint32_t B,
+                             uint32_t L, uint32_t *d_out, uint32_t flags, void *stream);
+
 /* One job of fdfb_bootstrap_multi: a batch on its own context (its own
  * parameter set, e.g. a different N). */
 typedef struct fdfb_job {
@@ -132,7 +150,8 @@ typedef struct fdfb_job {
 /*
  * Bootstrap several jobs (mixed parameter sets and lookup tables) as one
  * stream-ordered submission.  Equivalent, output for output, to calling
- * fdfb_bootstrap_batch on each job.  Errors as fdfb_bootstrap_batch.
+ * fdfb_bootstrap_batch on each job, in order on `stream`; every job is
+ * validated before anything is enqueued.  Errors as fdfb_bootstrap_batch.
  */
 int fdfb_bootstrap_multi(const fdfb_job *jobs, uint32_t njobs, void *stream);
 

@@ -447,27 +447,34 @@ int ensure_device(fdfb_ctx &c)
 }
 
 
-size_t Scratch::bytes_for(const fdfb_params &P, uint32_t B)
+size_t Scratch::bytes_for(const fdfb_params &P, uint32_t B, uint32_t L)
 {
-    const size_t n1 = P.n + 1, N = P.N, eb = P.boot_ell;
-    return 4 * (B * n1 + B * eb * 2 * N + B * eb * (N + 1) + B * eb * 2 * N + B * 2 * N + B * (N + 1));
+    const size_t n1 = P.n + 1, N = P.N, eb = P.boot_ell, E = (size_t)B * L;
+    return 4 * (B * n1 + B * eb * 2 * N + B * eb * (N + 1) + B * eb * 2 * N + E * 2 * N + E * (N + 1));
 }
 
 void Scratch::release()
 {
+    if (ctN || acc_sign || cbits || rbits || accf || cq)
+        (void)hipDeviceSynchronize();  // launches on any stream may still use the buffers
     for (uint32_t *p : {ctN, acc_sign, cbits, rbits, accf, cq})
         if (p) (void)hipFree(p);
     ctN = acc_sign = cbits = rbits = accf = cq = nullptr;
-    cap = 0;
+    cap = capf = 0;
 }
 
-int ensure_scratch(fdfb_ctx &c, Scratch &sc, uint32_t B)
+int ensure_scratch(fdfb_ctx &c, Scratch &sc, uint32_t B, uint32_t L)
 {
-    if (B <= sc.cap) return FDFB_OK;
+    const uint64_t E64 = (uint64_t)B * L;
+    if (E64 > 0xFFFFFFFFu) return fail(FDFB_EINVAL, "too many table evaluations in one call");
+    const uint32_t E = (uint32_t)E64;
+    if (B <= sc.cap && E <= sc.capf) return FDFB_OK;
+    B = std::max(B, sc.cap);
+    const size_t Ef = std::max(E, sc.capf);
     sc.release();
     const size_t n1 = c.P.n + 1, N = c.P.N, eb = c.P.boot_ell;
     uint32_t **bufs[] = {&sc.ctN, &sc.acc_sign, &sc.cbits, &sc.rbits, &sc.accf, &sc.cq};
-    const size_t words[] = {B * n1, B * eb * 2 * N, B * eb * (N + 1), B * eb * 2 * N, B * 2 * N, B * (N + 1)};
+    const size_t words[] = {B * n1, B * eb * 2 * N, B * eb * (N + 1), B * eb * 2 * N, Ef * 2 * N, Ef * (N + 1)};
     for (int k = 0; k < 6; ++k) {
         hipError_t e = hipMalloc((void **)bufs[k], words[k] * 4);
         if (e != hipSuccess) {
@@ -477,6 +484,7 @@ int ensure_scratch(fdfb_ctx &c, Scratch &sc, uint32_t B)
         }
     }
     sc.cap = B;
+    sc.capf = (uint32_t)Ef;
     return FDFB_OK;
 }
 
@@ -521,11 +529,12 @@ int check_form(const fdfb_ctx &c, uint32_t flags)
     } while (0)
 
 int bootstrap_with(fdfb_ctx &c, Scratch &sc, const uint32_t *d_cts, const int32_t *d_ids, uint32_t B,
-                   uint32_t *d_out, uint32_t flags, hipStream_t st)
+                   uint32_t *d_out, uint32_t flags, hipStream_t st, uint32_t L)
 {
     int rc;
     if ((rc = ensure_device(c))) return rc;
-    if ((rc = ensure_scratch(c, sc, B))) return rc;
+    if ((rc = ensure_scratch(c, sc, B, L))) return rc;
+    const uint32_t E = B * L;  // table evaluations, sample-major: e = b L + l
     const fdfbk::Geometry &G = c.geom;
     const uint32_t eb = G.boot_ell, N = G.N;
     const uint32_t half = 1u << (31 - G.log2_t);
@@ -546,20 +555,21 @@ int bootstrap_with(fdfb_ctx &c, Scratch &sc, const uint32_t *d_cts, const int32_
     // 3. bit samples: SampleExtract + L_boot^i Delta/2
     K_TRY(fdfbk::launch_extract(G, sc.acc_sign, B * eb, eb, half, sc.cbits, st));
     K_TRY(mark(3));
-    // 4. BuildAcc: LWE -> RLWE switching, then the public mux
+    // 4. BuildAcc: LWE -> RLWE switching, then the public mux (one accumulator
+    //    per table; the bit samples are shared by the tables of a sample)
     K_TRY(run_ks(c, true, sc.cbits, B * eb, sc.rbits, st));
     K_TRY(mark(4));
-    K_TRY(fdfbk::launch_pubmux(G, sc.rbits, sc.ctN, d_ids, B, c.d_luts, c.nluts, sc.accf, st));
+    K_TRY(fdfbk::launch_pubmux(G, sc.rbits, sc.ctN, d_ids, E, L, c.d_luts, c.nluts, sc.accf, st));
     K_TRY(mark(5));
-    // 5. function blind rotation
-    K_TRY(run_br(c, sc.accf, sc.ctN, B, 1, flags, st));
+    // 5. function blind rotations, L per sample
+    K_TRY(run_br(c, sc.accf, sc.ctN, E, L, flags, st));
     K_TRY(mark(6));
     // 6. SampleExtract, then LWE(N) -> LWE(n) unless the extracted form is requested
     if (flags & FDFB_OUT_EXTRACTED) {
-        K_TRY(fdfbk::launch_extract(G, sc.accf, B, 1, 0, d_out, st));
+        K_TRY(fdfbk::launch_extract(G, sc.accf, E, 1, 0, d_out, st));
     } else {
-        K_TRY(fdfbk::launch_extract(G, sc.accf, B, 1, 0, sc.cq, st));
-        K_TRY(run_ks(c, false, sc.cq, B, d_out, st));
+        K_TRY(fdfbk::launch_extract(G, sc.accf, E, 1, 0, sc.cq, st));
+        K_TRY(run_ks(c, false, sc.cq, E, d_out, st));
     }
     K_TRY(mark(7));
     return FDFB_OK;
@@ -624,13 +634,40 @@ int fdfb_bootstrap_batch(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *d_lu
     return bootstrap_with(*c, c->scratch, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream);
 }
 
+int fdfb_bootstrap_multi_lut(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *d_lut_ids, uint32_t B,
+                             uint32_t L, uint32_t *d_out, uint32_t flags, void *stream)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    if (c->abort_flag.load()) return fail(FDFB_EABORTED, "abort flag raised");
+    if (L == 0) return fail(FDFB_EINVAL, "at least one table per sample");
+    if (B == 0) return FDFB_OK;
+    if (!d_cts || !d_lut_ids || !d_out) return fail(FDFB_EINVAL, "null buffer");
+    if (flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+    if (int rc = check_form(*c, flags)) return rc;
+    return bootstrap_with(*c, c->scratch, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream, L);
+}
+
 int fdfb_bootstrap_multi(const fdfb_job *jobs, uint32_t njobs, void *stream)
 {
     if (njobs && !jobs) return fail(FDFB_EINVAL, "null jobs");
+    // validate every job before anything is enqueued
     for (uint32_t k = 0; k < njobs; ++k) {
-        int rc = fdfb_bootstrap_batch(jobs[k].ctx, jobs[k].d_cts, jobs[k].d_lut_ids, jobs[k].B,
-                                      jobs[k].d_out, jobs[k].flags, stream);
-        if (rc) return rc;
+        const fdfb_job &j = jobs[k];
+        if (!j.ctx) return fail(FDFB_EINVAL, "null context in job");
+        if (j.ctx->abort_flag.load()) return fail(FDFB_EABORTED, "abort flag raised");
+        if (j.B == 0) continue;
+        if (!j.d_cts || !j.d_lut_ids || !j.d_out) return fail(FDFB_EINVAL, "null buffer in job");
+        if (j.flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+        if (int rc = check_form(*j.ctx, j.flags)) return rc;
+    }
+    // each job's launches already fill the device (measured: running the jobs
+    // of different contexts concurrently on separate streams was 3% slower)
+    for (uint32_t k = 0; k < njobs; ++k) {
+        const fdfb_job &j = jobs[k];
+        if (j.B == 0) continue;
+        if (int rc = bootstrap_with(*j.ctx, j.ctx->scratch, j.d_cts, j.d_lut_ids, j.B, j.d_out, j.flags,
+                                    (hipStream_t)stream))
+            return rc;
     }
     return FDFB_OK;
 }
@@ -698,7 +735,7 @@ int fdfb_pubmux(fdfb_ctx *c, const uint32_t *d_rlwe, const uint32_t *d_ctN, cons
     if (!d_rlwe || !d_ctN || !d_lut_ids || !d_acc) return fail(FDFB_EINVAL, "null buffer");
     int rc = ensure_device(*c);
     if (rc) return rc;
-    K_TRY(fdfbk::launch_pubmux(c->geom, d_rlwe, d_ctN, d_lut_ids, B, c->d_luts, c->nluts, d_acc,
+    K_TRY(fdfbk::launch_pubmux(c->geom, d_rlwe, d_ctN, d_lut_ids, B, 1, c->d_luts, c->nluts, d_acc,
                                (hipStream_t)stream));
     return FDFB_OK;
 }

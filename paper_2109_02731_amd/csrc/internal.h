@@ -15,10 +15,11 @@ namespace fdfbi {
 // Device scratch of one bootstrap batch: ModSwitched samples, sign
 // accumulators, bit samples, switched RLWE samples, built accumulators, c_Q.
 struct Scratch {
-    uint32_t cap = 0;  // capacity in samples
+    uint32_t cap = 0;   // capacity in samples
+    uint32_t capf = 0;  // capacity in table evaluations (samples x tables per sample)
     uint32_t *ctN = nullptr, *acc_sign = nullptr, *cbits = nullptr, *rbits = nullptr, *accf = nullptr,
              *cq = nullptr;
-    static size_t bytes_for(const fdfb_params &P, uint32_t B);
+    static size_t bytes_for(const fdfb_params &P, uint32_t B, uint32_t L = 1);
     void release();
     ~Scratch() { release(); }
 };
@@ -67,11 +68,12 @@ namespace fdfbi {
 int fail(int code, const std::string &msg);
 // Upload keys and registered tables on first use (or after new tables).
 int ensure_device(fdfb_ctx &c);
-int ensure_scratch(fdfb_ctx &c, Scratch &sc, uint32_t B);
+int ensure_scratch(fdfb_ctx &c, Scratch &sc, uint32_t B, uint32_t L = 1);
 // The requested blind-rotation form must exist for the context's parameters.
 int check_form(const fdfb_ctx &c, uint32_t flags);
-// Enqueue one full bootstrap batch on `st` using scratch `sc`.
+// Enqueue one full bootstrap batch on `st` using scratch `sc`: L tables per
+// sample (ids [B][L], outputs [B][L][dim]) share the sign rotations.
 int bootstrap_with(fdfb_ctx &c, Scratch &sc, const uint32_t *d_cts, const int32_t *d_ids, uint32_t B,
-                   uint32_t *d_out, uint32_t flags, hipStream_t st);
+                   uint32_t *d_out, uint32_t flags, hipStream_t st, uint32_t L = 1);
 
 }  // namespace fdfbi

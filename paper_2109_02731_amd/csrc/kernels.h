@@ -47,8 +47,10 @@ hipError_t launch_keyswitch_mfma(const uint32_t *in, uint32_t B, uint32_t din, c
                                  int ell, uint32_t out_len, uint32_t *out, hipStream_t s);
 hipError_t launch_affine(const int32_t *W, const uint32_t *in, uint32_t rows, uint32_t cols, uint32_t width,
                          uint32_t *out, hipStream_t s);
+// E table evaluations; evaluation e uses sample e / per (its RLWE bit samples
+// and ModSwitched sample) and table lut_ids[e].
 hipError_t launch_pubmux(const Geometry &G, const uint32_t *rlwe, const uint32_t *ctN,
-                         const int32_t *lut_ids, uint32_t B, const int32_t *luts, int nluts,
+                         const int32_t *lut_ids, uint32_t E, uint32_t per, const int32_t *luts, int nluts,
                          uint32_t *acc, hipStream_t s);
 
 }  // namespace fdfbk

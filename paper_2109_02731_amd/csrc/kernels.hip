@@ -270,14 +270,15 @@ __global__ __launch_bounds__(256) void k_pubmux(const uint32_t *__restrict__ rlw
                                                 const int32_t *__restrict__ lut_ids,
                                                 const int32_t *__restrict__ luts, int nluts,
                                                 uint32_t *__restrict__ acc, int n, int N,
-                                                int log2_t, int boot_log2B, int ellb)
+                                                int log2_t, int boot_log2B, int ellb, uint32_t per)
 {
     extern __shared__ uint8_t smem[];
     int8_t *dx = (int8_t *)smem;                              // [ellb][2N]
     uint32_t *pa = (uint32_t *)(smem + ((ellb * 2 * N + 15) & ~15));  // [N] Delta * p_A
-    const uint32_t b = blockIdx.x;
-    const int id = lut_ids[b];
-    uint32_t *o = acc + (size_t)b * 2 * N;
+    const uint32_t eidx = blockIdx.x;  // table evaluation: sample eidx / per, its own table
+    const uint32_t b = eidx / per;
+    const int id = lut_ids[eidx];
+    uint32_t *o = acc + (size_t)eidx * 2 * N;
     if (id < 0 || id >= nluts) {  // unknown table: defined, all-zero output
         for (int m = threadIdx.x; m < 2 * N; m += blockDim.x) o[m] = 0;
         return;
@@ -994,13 +995,14 @@ hipError_t launch_affine(const int32_t *W, const uint32_t *in, uint32_t rows, ui
 }
 
 hipError_t launch_pubmux(const Geometry &G, const uint32_t *rlwe, const uint32_t *ctN,
-                         const int32_t *lut_ids, uint32_t B, const int32_t *luts, int nluts,
+                         const int32_t *lut_ids, uint32_t E, uint32_t per, const int32_t *luts, int nluts,
                          uint32_t *acc, hipStream_t s)
 {
-    if (!B) return hipSuccess;
+    if (!E) return hipSuccess;
+    if (!per) return hipErrorInvalidValue;
     const size_t lds = ((size_t)(G.boot_ell * 2 * G.N + 15) & ~(size_t)15) + 4 * (size_t)G.N;
-    hipLaunchKernelGGL(k_pubmux, dim3(B), dim3(256), lds, s, rlwe, ctN, lut_ids, luts, nluts, acc,
-                       G.n, G.N, G.log2_t, G.boot_log2B, G.boot_ell);
+    hipLaunchKernelGGL(k_pubmux, dim3(E), dim3(256), lds, s, rlwe, ctN, lut_ids, luts, nluts, acc,
+                       G.n, G.N, G.log2_t, G.boot_log2B, G.boot_ell, per);
     return hipGetLastError();
 }
 

@@ -336,3 +336,64 @@ def test_br_launch_count(c2):
     assert ctx.br_launches(1 << 16, 2, flags=fd.PLAIN) == 1
     with pytest.raises(fd.FdfbError):
         ctx.br_launches(4, 0)
+
+
+@pytest.mark.parametrize("flags", [0, fd.OUT_EXTRACTED])
+def test_multi_lut_shares_sign_rotations(c1, flags):
+    """Several tables per sample (sign accumulators reused): every output is
+    bit-identical to the single-table bootstrap of that sample and table, and
+    decrypts to the table's value."""
+    ctx, ok = c1
+    p = W.C1
+    L = 3
+    tables = [W.random_lut(900 + l, p.t) for l in range(L)]
+    lids = [ctx.register_lut(tb) for tb in tables]
+    msgs = np.arange(p.t, dtype=np.uint32).repeat(2)
+    B = len(msgs)
+    cts = fd.to_device(ctx.encrypt_debug(msgs, seed=77))
+    rng = np.random.default_rng(5)
+    pick = rng.integers(0, L, (B, L)).astype(np.int32)  # a table per (sample, slot), repeats allowed
+    ids = torch.from_numpy(np.array(lids, dtype=np.int32)[pick]).cuda()
+    dim = (p.N if flags else p.n) + 1
+    out = torch.zeros((B, L, dim), dtype=torch.int32, device="cuda")
+    ctx.bootstrap_multi_lut(cts, ids, out, flags)
+    torch.cuda.synchronize()
+    got = fd.to_host(out)
+    for l in range(L):
+        single = torch.zeros((B, dim), dtype=torch.int32, device="cuda")
+        ctx.bootstrap_batch(cts, ids[:, l].contiguous(), single, flags)
+        torch.cuda.synchronize()
+        assert np.array_equal(fd.to_host(single), got[:, l, :]), l
+        if not flags:
+            m, _ = ctx.decrypt_debug(got[:, l, :])
+            want = np.array([tables[pick[b, l]][msgs[b]] for b in range(B)])
+            assert np.array_equal(m, want), l
+    # one output against the oracle, bit for bit
+    b, l = 5, 2
+    r0, r1 = oracle.setup_polynomial(tables[pick[b, l]], p.N)
+    ref = oracle.fdfb(ok, r0, r1, fd.to_host(cts)[b], flags=oracle.OUT_EXTRACTED if flags else 0)
+    assert np.array_equal(got[b, l], ref)
+
+
+def test_multi_lut_c2_and_errors(c2):
+    ctx, _ = c2
+    p = W.C2
+    L, B = 4, 64
+    tables = [W.random_lut(950 + l, p.t) for l in range(L)]
+    lids = np.array([ctx.register_lut(tb) for tb in tables], dtype=np.int32)
+    msgs = W.messages(123, B, p.t)
+    cts = fd.to_device(ctx.encrypt_debug(msgs, seed=124))
+    ids = torch.from_numpy(np.tile(lids, (B, 1))).cuda()
+    out = torch.zeros((B, L, p.n + 1), dtype=torch.int32, device="cuda")
+    ctx.bootstrap_multi_lut(cts, ids, out)
+    torch.cuda.synchronize()
+    got = fd.to_host(out)
+    for l in range(L):
+        single = torch.zeros((B, p.n + 1), dtype=torch.int32, device="cuda")
+        ctx.bootstrap_batch(cts, ids[:, l].contiguous(), single)
+        torch.cuda.synchronize()
+        assert np.array_equal(fd.to_host(single), got[:, l, :]), l
+        assert np.array_equal(ctx.decrypt_debug(got[:, l, :])[0], tables[l][msgs]), l
+    with pytest.raises(fd.FdfbError):
+        ctx.bootstrap_multi_lut(cts, ids[:, :0].contiguous(), out)  # L = 0
+    ctx.bootstrap_multi_lut(cts[:0], ids[:0], out[:0])  # B = 0 is a no-op
