@@ -382,6 +382,9 @@ uint32_t or_decrypt(const uint32_t *ct, const uint32_t *key, uint32_t dim, uint3
 /* Reading R7: Delta * t = 0 mod 2^32, so only p mod t matters; the digits   */
 /* are the unsigned base-L_boot digits of (p mod t), ell_boot = ceil(log_L t)*/
 /* of them (boot_ell).                                                       */
+/* Variant (boot_log2B = 0, boot_ell = 1): one signed digit, the centred     */
+/* representative of (p mod t) in [-t/2, t/2); Delta * t = 0 mod 2^32 keeps  */
+/* the plaintext Delta * p_bit, with one sign rotation instead of ell_boot.  */
 /* c: ell_boot RLWE samples [2][N]; p0, p1 small signed polynomials.         */
 /* ------------------------------------------------------------------------ */
 void or_pubmux(const or_params *P, const uint32_t *c, const int64_t *p0, const int64_t *p1,
@@ -401,7 +404,12 @@ void or_pubmux(const or_params *P, const uint32_t *c, const int64_t *p0, const i
         for (uint32_t m = 0; m < N; ++m) {
             int64_t p = p1[m] - p0[m];
             uint64_t pm = (uint64_t)(((p % (int64_t)t) + (int64_t)t) % (int64_t)t);
-            dig[m] = (uint32_t)((pm / Li) % L);
+            if (P->boot_log2B == 0) {
+                int64_t cen = (int64_t)pm >= (int64_t)(t / 2) ? (int64_t)pm - (int64_t)t : (int64_t)pm;
+                dig[m] = (uint32_t)cen; /* two's complement, mod 2^32 */
+            } else {
+                dig[m] = (uint32_t)((pm / Li) % L);
+            }
         }
         for (uint32_t comp = 0; comp < 2; ++comp) {
             or_negacyclic_mul(dig, c + ((size_t)i * 2 + comp) * N, tmp, N);

@@ -10,6 +10,8 @@ measured noise variance against the error analysis.
 """
 from fractions import Fraction
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -252,6 +254,29 @@ def test_pubmux_selects(bit):
     assert np.array_equal(rlwe_phase(out, key), ((sel * delta) % M32).astype(np.uint32))
 
 
+def test_pubmux_signed_digit_is_centred():
+    """The single signed digit: muxing with the trivial sample [1, 0] leaves
+    out - Delta p_0 = digit, which must be the representative of
+    (p_1 - p_0) mod t in [-t/2, t/2) (an unsigned digit in [0, t) would also
+    select correctly in the noise-free limit, so this pins the reading)."""
+    p = W.signed_boot(W.C2)
+    N, t = p.N, p.t
+    delta = M32 // t
+    g = rnd(41)
+    p0 = g.integers(-(t - 1), t, N).astype(np.int64)
+    p1 = g.integers(-(t - 1), t, N).astype(np.int64)
+    c = np.zeros((1, 2 * N), np.uint32)
+    c[0, 0] = 1  # b = 1, a = 0: a_i(X) * 1 is the digit polynomial itself
+    out = oracle.pubmux(p, c, p0, p1).astype(np.int64)
+    dig = (out[:N] - (p0 * delta) % M32) % M32
+    dig = np.where(dig >= M32 // 2, dig - M32, dig)
+    want = (p1 - p0) % t
+    want = np.where(want >= t // 2, want - t, want)
+    assert np.array_equal(dig, want)
+    assert dig.min() >= -(t // 2) and dig.max() < t // 2 and (dig < 0).any()
+    assert not out[N:].any()
+
+
 # ----------------------------------------------------------------------------
 # the full bootstrap
 # ----------------------------------------------------------------------------
@@ -297,6 +322,38 @@ def test_fdfb_full_domain_c2(oracle_keys_c2):
     msgs = np.arange(t, dtype=np.uint32)
     cts = oracle.encrypt(p, k.s, msgs, seed=W.MSG_SEED["C2"])
     lut = W.random_lut(W.LUT_SEED["C2"], t)
+    rot = [oracle.setup_polynomial(lut, p.N)]
+    outs = oracle.fdfb_batch(k, rot, np.zeros(t, int), cts)
+    m, err = oracle.decrypt(outs, k.s, p.log2_t)
+    assert np.array_equal(m, lut[msgs])
+    assert np.max(np.abs(err)) < (M32 // t) // 4
+
+
+def test_signed_boot_digit_noise_free_exact(oracle_keys_c1_exact):
+    """Variant with one signed public-mux digit: since Delta * t = 0 mod 2^32,
+    the centred digit of (p_1 - p_0) mod t selects the same plaintext, so the
+    noise-free output phase is still exactly Delta * f(m) for every m."""
+    k = dataclasses.replace(oracle_keys_c1_exact, params=W.signed_boot(oracle_keys_c1_exact.params))
+    p = k.params
+    t, delta = p.t, M32 // p.t
+    msgs = np.arange(t, dtype=np.uint32)
+    cts = oracle.encrypt(p, k.s, msgs, seed=6)
+    for name, lut in _luts(t, 78).items():
+        r0, r1 = oracle.setup_polynomial(lut, p.N)
+        for m in range(t):
+            out = oracle.fdfb(k, r0, r1, cts[m])
+            assert lwe_phase(out, k.s) == (delta * int(lut[m])) % M32, (name, m)
+
+
+def test_signed_boot_digit_full_domain_c2(oracle_keys_c2):
+    """The variant at configuration-2 noise: every m decrypts to f(m), and the
+    PubMux stage dump differs from the unsigned reading (the digit is used)."""
+    k = dataclasses.replace(oracle_keys_c2, params=W.signed_boot(oracle_keys_c2.params))
+    p = k.params
+    t = p.t
+    msgs = np.arange(t, dtype=np.uint32)
+    cts = oracle.encrypt(p, k.s, msgs, seed=W.MSG_SEED["C2"] + 1)
+    lut = W.random_lut(W.LUT_SEED["C2"] + 1, t)
     rot = [oracle.setup_polynomial(lut, p.N)]
     outs = oracle.fdfb_batch(k, rot, np.zeros(t, int), cts)
     m, err = oracle.decrypt(outs, k.s, p.log2_t)

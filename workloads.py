@@ -101,6 +101,13 @@ def exact(p: Params) -> Params:
                    g_log2B=8, g_ell=4, ks_log2B=4, ks_ell=8, pk_log2B=4, pk_ell=8)
 
 
+def signed_boot(p: Params) -> Params:
+    """Variant with one signed public-mux digit in [-t/2, t/2) (encoded as
+    boot_log2B = 0, boot_ell = 1): one sign rotation per bootstrap instead of
+    ell_boot, at the price of a digit up to t/2 in magnitude."""
+    return p.with_(boot_log2B=0, boot_ell=1)
+
+
 def messages(seed: int, count: int, t: int) -> np.ndarray:
     """Uniform plaintexts in Z_t."""
     rng = np.random.default_rng(seed)
