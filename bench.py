@@ -48,9 +48,15 @@ def br_ops_per_accumulator(p) -> float:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the blind-rotation kernel's source: the kernel itself and its
+    launcher (other kernels in the same file do not change its traffic)."""
+    with open(os.path.join(ROOT, "paper_2109_02731_amd", "csrc", "kernels.hip")) as f:
+        src = f.read()
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2109_02731_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for start, end in (("struct BrKara {", "// launchers"),
+                       ("static hipError_t br_kara_capacity", "bool br_mfma_supported")):
+        a = src.index(start)
+        h.update(src[a:src.index(end, a)].encode())
     return h.hexdigest()[:16]
 
 
@@ -207,6 +213,30 @@ def multi_lut_bench(fd, torch, W, ctx, p, d_cts, B: int, L: int, steps: int, sin
             "speedup_vs_single_table_calls": L * single_ms / (dt * 1e3), "steps": steps}
 
 
+def signed_boot_bench(fd, torch, W, B: int, steps: int):
+    """Variant with one signed public-mux digit (one sign rotation per
+    sample): bootstraps/s on the bench batch, outputs decrypted."""
+    p = W.signed_boot(W.C2)
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C2"])
+    lut = W.random_lut(W.LUT_SEED["C2"], p.t)
+    lid = ctx.register_lut(lut)
+    msgs = W.messages(W.MSG_SEED["C2"], B, p.t)
+    cts = fd.to_device(ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C2"]))
+    ids = torch.full((B,), lid, dtype=torch.int32, device="cuda")
+    out = torch.empty((B, p.n + 1), dtype=torch.int32, device="cuda")
+    ctx.bootstrap_batch(cts, ids, out)
+    torch.cuda.synchronize()
+    correct = bool(np.array_equal(ctx.decrypt_debug(fd.to_host(out))[0], lut[msgs]))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.bootstrap_batch(cts, ids, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"bootstraps_per_s": B / dt, "ms_per_step": dt * 1e3, "blind_rotations_per_bootstrap": 2,
+            "correct": correct, "steps": steps,
+            "note": "variant, not the paper's digit reading: one signed public-mux digit in [-t/2, t/2)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +249,8 @@ def main():
                     help="requests per serving run (0 skips the serving measurement)")
     ap.add_argument("--multi-lut", type=int, default=4, metavar="L",
                     help="also time L tables per sample on the bench batch (0 skips)")
+    ap.add_argument("--signed-boot-steps", type=int, default=5,
+                    help="also time the one-signed-digit variant this many steps (0 skips)")
     ap.add_argument("--mixed-steps", type=int, default=0,
                     help="also time the uneven two-degree batch (one multi-job submission) this many times")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -321,6 +353,11 @@ def main():
         print(f"[bench] {args.multi_lut} tables per sample", file=sys.stderr, flush=True)
         multi_lut = multi_lut_bench(fd, torch, W, ctx, p, d_cts, B, args.multi_lut, 3, wall / K * 1e3)
 
+    signed = None
+    if args.signed_boot_steps > 0:
+        print("[bench] signed boot digit variant", file=sys.stderr, flush=True)
+        signed = signed_boot_bench(fd, torch, W, B, args.signed_boot_steps)
+
     mixed = None
     if args.mixed_steps > 0:
         print("[bench] uneven two-degree batch", file=sys.stderr, flush=True)
@@ -362,6 +399,7 @@ def main():
         "roofline": roofline,
         "serving": serving,
         "multi_lut": multi_lut,
+        "signed_boot_digit": signed,
         "mixed": mixed,
         "cpu_baseline": cpu,
     }

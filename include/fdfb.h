@@ -58,7 +58,9 @@ extern "C" {
  *   g_*       blind-rotation key gadget (L_RGSW)
  *   ks_*      key switching key LWE(s_F, N) -> LWE(s, n)
  *   pk_*      packing key LWE(s_F, N) -> RLWE(s_F)
- *   boot_*    public-mux digits: base L_boot, ell_boot = ceil(log_Lboot t)
+ *   boot_*    public-mux digits: base L_boot, ell_boot = ceil(log_Lboot t);
+ *             boot_log2B = 0 with boot_ell = 1 (t <= 128) selects one signed
+ *             digit in [-t/2, t/2): one sign rotation per bootstrap
  *   sigma_*   noise standard deviations in units of 1 (q = 2^32): fresh LWE
  *             samples, blind-rotation key, packing key, key switching key
  */

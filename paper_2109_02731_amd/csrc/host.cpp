@@ -158,8 +158,12 @@ int check_params(const fdfb_params &P)
             return fail(FDFB_EINVAL, std::string(g.name) + ": need 1 <= ell, 1 <= log2B, ell*log2B <= 32");
     if (P.g_log2B > 14) return fail(FDFB_EINVAL, "gadget base above 2^14 is not supported");
     if (P.ks_ell > 8 || P.pk_ell > 8) return fail(FDFB_EINVAL, "key switching ell above 8 is not supported");
-    if (P.boot_log2B < 1 || P.boot_log2B > 7 || P.boot_ell < 1 || P.boot_ell * P.boot_log2B < P.log2_t)
+    if (P.boot_log2B == 0) {  // one signed digit in [-t/2, t/2)
+        if (P.boot_ell != 1 || P.log2_t > 7)
+            return fail(FDFB_EINVAL, "a signed boot digit needs boot_ell = 1 and t <= 128");
+    } else if (P.boot_log2B > 7 || P.boot_ell < 1 || P.boot_ell * P.boot_log2B < P.log2_t) {
         return fail(FDFB_EINVAL, "boot digits must cover t: boot_ell * boot_log2B >= log2_t, log2B in [1,7]");
+    }
     if (!(P.sigma_lwe >= 0) || !(P.sigma_glwe >= 0) || !(P.sigma_pk >= 0) || !(P.sigma_ks >= 0))
         return fail(FDFB_EINVAL, "noise deviations must be non-negative");
     if (!plain_br_fits(P) && !fdfbk::br_mfma_supported(geometry_of(P)))

@@ -294,7 +294,8 @@ __global__ __launch_bounds__(256) void k_pubmux(const uint32_t *__restrict__ rlw
         int32_t p = (vb - va) % t;
         if (p < 0) p += t;
         for (int i = 0; i < ellb; ++i) {
-            int32_t d = (p >> (boot_log2B * i)) & ((1 << boot_log2B) - 1);
+            // unsigned base-L_boot digits, or (boot_log2B = 0) one centred digit
+            int32_t d = boot_log2B ? (p >> (boot_log2B * i)) & ((1 << boot_log2B) - 1) : (p >= t / 2 ? p - t : p);
             dx[i * 2 * N + N + m] = (int8_t)d;   // position m
             dx[i * 2 * N + m] = (int8_t)(-d);    // position m - N
         }

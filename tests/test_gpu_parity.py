@@ -1,5 +1,7 @@
 """GPU parity: every stage of the HIP path against the CPU oracle, bit for bit,
 through the C ABI, for both kernel forms (batched MFMA and plain VALU)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -397,3 +399,49 @@ def test_multi_lut_c2_and_errors(c2):
     with pytest.raises(fd.FdfbError):
         ctx.bootstrap_multi_lut(cts, ids[:, :0].contiguous(), out)  # L = 0
     ctx.bootstrap_multi_lut(cts[:0], ids[:0], out[:0])  # B = 0 is a no-op
+
+
+def test_signed_boot_digit_c1_vs_oracle(oracle_keys_c1):
+    """Variant with one signed public-mux digit (one sign rotation): bit for
+    bit against the oracle, both forms, and full-domain decryption."""
+    p = W.signed_boot(W.C1)
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C1"])
+    ok = dataclasses.replace(oracle_keys_c1, params=p)
+    lut = W.random_lut(W.LUT_SEED["C1"] + 5, p.t)
+    lid = ctx.register_lut(lut)
+    msgs = np.arange(p.t, dtype=np.uint32).repeat(2)
+    cts = ctx.encrypt_debug(msgs, seed=31)
+    r0, r1 = oracle.setup_polynomial(lut, p.N)
+    refs = np.stack([oracle.fdfb(ok, r0, r1, c) for c in cts])
+    for flags in (0, fd.PLAIN):
+        out = torch.zeros((len(msgs), p.n + 1), dtype=torch.int32, device="cuda")
+        ctx.bootstrap_batch(fd.to_device(cts), torch.full((len(msgs),), lid, dtype=torch.int32, device="cuda"),
+                            out, flags)
+        torch.cuda.synchronize()
+        got = fd.to_host(out)
+        assert np.array_equal(got, refs), flags
+        assert np.array_equal(ctx.decrypt_debug(got)[0], lut[msgs])
+
+
+def test_signed_boot_digit_c2_batch(c2):
+    """The variant at configuration 2 on a full batch: every sample decrypts
+    to f(m); sampled outputs match the oracle bit for bit; the sign phase
+    runs one rotation per sample."""
+    _, okc2 = c2
+    p = W.signed_boot(W.C2)
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C2"])
+    ok = dataclasses.replace(okc2, params=p)
+    lut = W.random_lut(W.LUT_SEED["C2"] + 5, p.t)
+    lid = ctx.register_lut(lut)
+    B = 1024
+    msgs = W.messages(W.MSG_SEED["C2"] + 5, B, p.t)
+    cts = ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C2"] + 5)
+    out = torch.zeros((B, p.n + 1), dtype=torch.int32, device="cuda")
+    ctx.bootstrap_batch(fd.to_device(cts), torch.full((B,), lid, dtype=torch.int32, device="cuda"), out)
+    torch.cuda.synchronize()
+    got = fd.to_host(out)
+    assert np.array_equal(ctx.decrypt_debug(got)[0], lut[msgs])
+    r0, r1 = oracle.setup_polynomial(lut, p.N)
+    for k in (0, 511, 1023):
+        assert np.array_equal(got[k], oracle.fdfb(ok, r0, r1, cts[k])), k
+    assert ctx.br_launches(B * p.boot_ell, p.boot_ell) == ctx.br_launches(B, 1)
