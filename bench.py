@@ -237,6 +237,22 @@ def signed_boot_bench(fd, torch, W, B: int, steps: int):
             "note": "variant, not the paper's digit reading: one signed public-mux digit in [-t/2, t/2)"}
 
 
+def tfhe_bench(fd, torch, ctx, d_cts, d_ids, B: int, steps: int, fdfb_ms: float):
+    """The one-rotation TFHE-style (half-domain) bootstrap on the same
+    kernels and batch: the yardstick for FDFB's extra rotations."""
+    out = torch.empty((B, ctx.params.n + 1), dtype=torch.int32, device="cuda")
+    ctx.tfhe_bootstrap_batch(d_cts, d_ids, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.tfhe_bootstrap_batch(d_cts, d_ids, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"bootstraps_per_s": B / dt, "ms_per_step": dt * 1e3, "blind_rotations_per_bootstrap": 1,
+            "fdfb_time_ratio": fdfb_ms / (dt * 1e3), "steps": steps,
+            "note": "half-domain only (m < t/2); FDFB's time over this is the price of the full domain"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +267,8 @@ def main():
                     help="also time L tables per sample on the bench batch (0 skips)")
     ap.add_argument("--signed-boot-steps", type=int, default=5,
                     help="also time the one-signed-digit variant this many steps (0 skips)")
+    ap.add_argument("--tfhe-steps", type=int, default=5,
+                    help="also time the one-rotation TFHE-style bootstrap this many steps (0 skips)")
     ap.add_argument("--mixed-steps", type=int, default=0,
                     help="also time the uneven two-degree batch (one multi-job submission) this many times")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -358,6 +376,11 @@ def main():
         print("[bench] signed boot digit variant", file=sys.stderr, flush=True)
         signed = signed_boot_bench(fd, torch, W, B, args.signed_boot_steps)
 
+    tfhe = None
+    if args.tfhe_steps > 0:
+        print("[bench] TFHE-style yardstick", file=sys.stderr, flush=True)
+        tfhe = tfhe_bench(fd, torch, ctx, d_cts, d_ids, B, args.tfhe_steps, wall / K * 1e3)
+
     mixed = None
     if args.mixed_steps > 0:
         print("[bench] uneven two-degree batch", file=sys.stderr, flush=True)
@@ -400,6 +423,7 @@ def main():
         "serving": serving,
         "multi_lut": multi_lut,
         "signed_boot_digit": signed,
+        "tfhe_yardstick": tfhe,
         "mixed": mixed,
         "cpu_baseline": cpu,
     }

@@ -138,6 +138,18 @@ int fdfb_bootstrap_batch(fdfb_ctx *ctx, const uint32_t *d_cts, const int32_t *d_
 int fdfb_bootstrap_multi_lut(fdfb_ctx *ctx, const uint32_t *d_cts, const int32_t *d_lut_ids, uint32_t B,
                              uint32_t L, uint32_t *d_out, uint32_t flags, void *stream);
 
+/*
+ * TFHE-style half-domain bootstrap (App. A Fig. "TFHE Bootstrapping"), the
+ * one-rotation yardstick for FDFB on the same kernels: acc = [Delta rotP_0
+ * X^{b_N}, 0] with rotP_0 of the sample's registered table, one blind
+ * rotation, SampleExtract, then the key switch (or the extracted sample with
+ * FDFB_OUT_EXTRACTED).  The result encrypts f(m) only for m < t/2; for
+ * m >= t/2 it encrypts -f(m - t/2), the limitation the full-domain bootstrap
+ * removes.  Arguments, layouts and errors as fdfb_bootstrap_batch.
+ */
+int fdfb_tfhe_bootstrap_batch(fdfb_ctx *ctx, const uint32_t *d_cts, const int32_t *d_lut_ids, uint32_t B,
+                              uint32_t *d_out, uint32_t flags, void *stream);
+
 /* One job of fdfb_bootstrap_multi: a batch on its own context (its own
  * parameter set, e.g. a different N). */
 typedef struct fdfb_job {

@@ -56,7 +56,7 @@ class _Job(C.Structure):
 
 EXPORTED = [
     "fdfb_keygen_from_seed", "fdfb_register_lut", "fdfb_bootstrap_batch", "fdfb_bootstrap_multi",
-    "fdfb_bootstrap_multi_lut",
+    "fdfb_bootstrap_multi_lut", "fdfb_tfhe_bootstrap_batch",
     "fdfb_keyswitch", "fdfb_modswitch", "fdfb_blind_rotate", "fdfb_sample_extract",
     "fdfb_packing_keyswitch", "fdfb_pubmux", "fdfb_encrypt_debug", "fdfb_decrypt_debug",
     "fdfb_export_keys", "fdfb_import_keys", "fdfb_get_key", "fdfb_profile", "fdfb_profile_read",
@@ -83,6 +83,7 @@ def lib():
             "fdfb_register_lut": (i, [P, P, P]),
             "fdfb_bootstrap_batch": (i, [P, P, P, u32, P, u32, P]),
             "fdfb_bootstrap_multi_lut": (i, [P, P, P, u32, u32, P, u32, P]),
+            "fdfb_tfhe_bootstrap_batch": (i, [P, P, P, u32, P, u32, P]),
             "fdfb_bootstrap_multi": (i, [P, u32, P]),
             "fdfb_keyswitch": (i, [P, P, u32, P, P]),
             "fdfb_modswitch": (i, [P, P, u32, P, P]),
@@ -244,6 +245,12 @@ class Context:
         L = int(lut_ids.shape[1]) if lut_ids.dim() == 2 else 0
         _check(lib().fdfb_bootstrap_multi_lut(self._h, _dev_ptr(cts, "cts"), _dev_ptr(lut_ids, "lut_ids"), B, L,
                                               _dev_ptr(out, "out"), flags, _stream(stream)))
+
+    def tfhe_bootstrap_batch(self, cts, lut_ids, out, flags: int = 0, stream=None):
+        """Half-domain (one-rotation) bootstrap with rotP_0 of each sample's table."""
+        B = int(cts.shape[0]) if cts.dim() > 1 else 0
+        _check(lib().fdfb_tfhe_bootstrap_batch(self._h, _dev_ptr(cts, "cts"), _dev_ptr(lut_ids, "lut_ids"), B,
+                                               _dev_ptr(out, "out"), flags, _stream(stream)))
 
     def bootstrap_batch(self, cts, lut_ids, out, flags: int = 0, stream=None):
         B = int(cts.shape[0]) if cts.dim() > 1 else 0

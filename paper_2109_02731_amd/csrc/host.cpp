@@ -651,6 +651,33 @@ int fdfb_bootstrap_multi_lut(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *
     return bootstrap_with(*c, c->scratch, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream, L);
 }
 
+int fdfb_tfhe_bootstrap_batch(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *d_lut_ids, uint32_t B,
+                              uint32_t *d_out, uint32_t flags, void *stream)
+{
+    if (!c) return fail(FDFB_EINVAL, "null context");
+    if (c->abort_flag.load()) return fail(FDFB_EABORTED, "abort flag raised");
+    if (B == 0) return FDFB_OK;
+    if (!d_cts || !d_lut_ids || !d_out) return fail(FDFB_EINVAL, "null buffer");
+    if (flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+    int rc;
+    if ((rc = check_form(*c, flags))) return rc;
+    if ((rc = ensure_device(*c))) return rc;
+    Scratch &sc = c->scratch;
+    if ((rc = ensure_scratch(*c, sc, B))) return rc;
+    const fdfbk::Geometry &G = c->geom;
+    const hipStream_t st = (hipStream_t)stream;
+    K_TRY(fdfbk::launch_modswitch(G, d_cts, B, sc.ctN, st));
+    K_TRY(fdfbk::launch_init_tfhe(G, sc.ctN, d_lut_ids, B, c->d_luts, c->nluts, sc.accf, st));
+    K_TRY(run_br(*c, sc.accf, sc.ctN, B, 1, flags, st));
+    if (flags & FDFB_OUT_EXTRACTED) {
+        K_TRY(fdfbk::launch_extract(G, sc.accf, B, 1, 0, d_out, st));
+    } else {
+        K_TRY(fdfbk::launch_extract(G, sc.accf, B, 1, 0, sc.cq, st));
+        K_TRY(run_ks(*c, false, sc.cq, B, d_out, st));
+    }
+    return FDFB_OK;
+}
+
 int fdfb_bootstrap_multi(const fdfb_job *jobs, uint32_t njobs, void *stream)
 {
     if (njobs && !jobs) return fail(FDFB_EINVAL, "null jobs");

@@ -24,6 +24,9 @@ hipError_t launch_modswitch(const Geometry &G, const uint32_t *cts, uint32_t B, 
                             hipStream_t s);
 hipError_t launch_init_sign(const Geometry &G, const uint32_t *ctN, uint32_t B, uint32_t *acc,
                             hipStream_t s);
+// [Delta rotP_0 X^{b_N}, 0] per sample (TFHE-style accumulator).
+hipError_t launch_init_tfhe(const Geometry &G, const uint32_t *ctN, const int32_t *lut_ids, uint32_t B,
+                            const int32_t *luts, int nluts, uint32_t *acc, hipStream_t s);
 hipError_t launch_br_plain(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
                            uint32_t accs_per_ct, const uint32_t *brk_raw, hipStream_t s);
 hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,

@@ -320,6 +320,31 @@ __global__ __launch_bounds__(256) void k_pubmux(const uint32_t *__restrict__ rlw
 }
 
 // ---------------------------------------------------------------------------
+// TFHE-style accumulator (App. A Fig. "TFHE Bootstrapping"): [Delta rotP_0
+// X^{b_N}, 0] for the table of each sample (zero for an unknown table).
+// ---------------------------------------------------------------------------
+__global__ void k_init_tfhe(const uint32_t *__restrict__ ctN, const int32_t *__restrict__ lut_ids,
+                            const int32_t *__restrict__ luts, int nluts, uint32_t *__restrict__ acc, int n,
+                            int N, int log2_t)
+{
+    const uint32_t b = blockIdx.y;
+    const int id = lut_ids[b];
+    const uint32_t e = ctN[(size_t)b * (n + 1)];
+    const uint32_t delta = 1u << (32 - log2_t);
+    uint32_t *row = acc + (size_t)b * 2 * N;
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x) {
+        uint32_t v = 0;
+        if (id >= 0 && id < nluts) {
+            const int32_t *r0 = luts + (size_t)id * 2 * N;
+            const uint32_t j = (uint32_t)(m + 2 * N - (int)e) % (2 * N);  // coefficient m of X^e r0
+            v = delta * (uint32_t)((j < (uint32_t)N) ? r0[j] : -r0[j - N]);
+        }
+        row[m] = v;
+        row[N + m] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Plain blind rotation (App. A Fig. "Blind Rotation"): one accumulator per
 // workgroup, schoolbook uint32 negacyclic products on the vector ALUs.
 // LDS: accumulator [2][N] u32, digits as signed extension [R][2N] int16,
@@ -939,6 +964,15 @@ hipError_t launch_init_sign(const Geometry &G, const uint32_t *ctN, uint32_t B, 
     const uint32_t half = 1u << (31 - G.log2_t);
     hipLaunchKernelGGL(k_init_sign, dim3((G.N + 255) / 256, B * G.boot_ell), dim3(256), 0, s, ctN,
                        acc, B, G.n, G.N, G.boot_ell, half, 1u << G.boot_log2B);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_tfhe(const Geometry &G, const uint32_t *ctN, const int32_t *lut_ids, uint32_t B,
+                            const int32_t *luts, int nluts, uint32_t *acc, hipStream_t s)
+{
+    if (!B) return hipSuccess;
+    hipLaunchKernelGGL(k_init_tfhe, dim3((G.N + 255) / 256, B), dim3(256), 0, s, ctN, lut_ids, luts, nluts, acc,
+                       G.n, G.N, G.log2_t);
     return hipGetLastError();
 }
 

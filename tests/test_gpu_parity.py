@@ -445,3 +445,36 @@ def test_signed_boot_digit_c2_batch(c2):
     for k in (0, 511, 1023):
         assert np.array_equal(got[k], oracle.fdfb(ok, r0, r1, cts[k])), k
     assert ctx.br_launches(B * p.boot_ell, p.boot_ell) == ctx.br_launches(B, 1)
+
+
+@pytest.mark.parametrize("form", ["batched", "plain"])
+def test_tfhe_half_domain_vs_oracle(c1, form):
+    """The one-rotation TFHE-style bootstrap on the same kernels: bit for bit
+    against the oracle, and the half-domain behaviour it has by construction."""
+    ctx, ok = c1
+    p = W.C1
+    t, delta = p.t, M32 // p.t
+    lut = W.random_lut(61, t)
+    lid = ctx.register_lut(lut)
+    msgs = np.arange(t, dtype=np.uint32).repeat(2)
+    cts = ctx.encrypt_debug(msgs, seed=62)
+    r0, _ = oracle.setup_polynomial(lut, p.N)
+    scaled = ((r0.astype(np.int64) * delta) % M32).astype(np.uint32)
+    flags = fd.PLAIN if form == "plain" else 0
+    for extracted in (0, fd.OUT_EXTRACTED):
+        dim = (p.N if extracted else p.n) + 1
+        out = torch.zeros((len(msgs), dim), dtype=torch.int32, device="cuda")
+        ctx.tfhe_bootstrap_batch(fd.to_device(cts), torch.full((len(msgs),), lid, dtype=torch.int32, device="cuda"),
+                                 out, flags | extracted)
+        torch.cuda.synchronize()
+        got = fd.to_host(out)
+        for k in (0, 5, 11, len(msgs) - 1):
+            ref = oracle.tfhe_bootstrap(ok, scaled, cts[k], flags=oracle.OUT_EXTRACTED if extracted else 0)
+            assert np.array_equal(got[k], ref), (extracted, k)
+        if not extracted:
+            m, _ = ctx.decrypt_debug(got)
+            for k, x in enumerate(msgs):
+                if x in (0, t // 2):
+                    continue  # on the wrap of the half-domain encoding
+                want = lut[x] if x < t // 2 else (-int(lut[x - t // 2])) % t
+                assert m[k] == want, (k, x)
