@@ -267,6 +267,8 @@ def main():
                     help="also time L tables per sample on the bench batch (0 skips)")
     ap.add_argument("--signed-boot-steps", type=int, default=5,
                     help="also time the one-signed-digit variant this many steps (0 skips)")
+    ap.add_argument("--direct-steps", type=int, default=3,
+                    help="also time the direct (non-Karatsuba) MFMA form this many steps (0 skips)")
     ap.add_argument("--tfhe-steps", type=int, default=5,
                     help="also time the one-rotation TFHE-style bootstrap this many steps (0 skips)")
     ap.add_argument("--mixed-steps", type=int, default=0,
@@ -376,6 +378,20 @@ def main():
         print("[bench] signed boot digit variant", file=sys.stderr, flush=True)
         signed = signed_boot_bench(fd, torch, W, B, args.signed_boot_steps)
 
+    direct = None
+    if args.direct_steps > 0:
+        print("[bench] direct (non-Karatsuba) MFMA form", file=sys.stderr, flush=True)
+        out_d = torch.empty_like(d_out)
+        ctx.bootstrap_batch(d_cts, d_ids, out_d, fd.DIRECT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.direct_steps):
+            ctx.bootstrap_batch(d_cts, d_ids, out_d, fd.DIRECT)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.direct_steps
+        direct = {"bootstraps_per_s": B / dt, "ms_per_step": dt * 1e3, "steps": args.direct_steps,
+                  "bit_identical_to_batched": bool(torch.equal(out_d, d_out))}
+
     tfhe = None
     if args.tfhe_steps > 0:
         print("[bench] TFHE-style yardstick", file=sys.stderr, flush=True)
@@ -424,6 +440,7 @@ def main():
         "multi_lut": multi_lut,
         "signed_boot_digit": signed,
         "tfhe_yardstick": tfhe,
+        "direct_form": direct,
         "mixed": mixed,
         "cpu_baseline": cpu,
     }

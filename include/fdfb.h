@@ -47,6 +47,11 @@ extern "C" {
                                    in Z_t": affine maps on c_Q before switching) */
 #define FDFB_PLAIN 0x2u         /* run the plain one-sample-per-workgroup
                                    VALU kernels instead of the batched MFMA ones */
+#define FDFB_DIRECT 0x4u        /* batched MFMA blind rotation without the
+                                   Karatsuba split: one N-size Toeplitz product
+                                   per digit row (a comparison form with the same
+                                   results; its key layout is built on first use).
+                                   Exclusive with FDFB_PLAIN (FDFB_EINVAL). */
 
 /*
  * Parameter set.  q = Q = 2^32 is fixed.  Gadget bases are powers of two,
@@ -109,7 +114,7 @@ int fdfb_register_lut(fdfb_ctx *ctx, const uint32_t *table, int32_t *lut_id);
  *   d_lut_ids  device int32[B], each a registered lut_id
  *   d_out      device uint32[B][n+1] (under s), or uint32[B][N+1] (under
  *              s_F) when FDFB_OUT_EXTRACTED is set
- *   flags      FDFB_OUT_EXTRACTED | FDFB_PLAIN (FDFB_ENOTSUP when the plain form
+ *   flags      FDFB_OUT_EXTRACTED | FDFB_PLAIN | FDFB_DIRECT (FDFB_ENOTSUP when the plain form
  *              cannot hold the parameter set, e.g. N = 2048 with ell = 4)
  * Scratch memory is taken from a pool owned by the context and grown on
  * demand (hipMalloc) the first time a larger B is seen.  B = 0 is a no-op.
@@ -186,7 +191,8 @@ int fdfb_modswitch(fdfb_ctx *ctx, const uint32_t *d_cts, uint32_t B, uint32_t *d
  * a in [A], acc_a <- CMux(brK[i], acc_a X^(-a_i), acc_a) for i = 1..n, where
  * a_i comes from row (a / accs_per_ct) of d_ctN.  d_acc uint32[A][2][N] is
  * updated in place; d_ctN uint32[A/accs_per_ct][n+1] (values in [0, 2N)).
- * flags: FDFB_PLAIN selects the VALU kernel.
+ * flags: FDFB_PLAIN selects the VALU kernel, FDFB_DIRECT the MFMA kernel
+ * without the Karatsuba split.
  */
 int fdfb_blind_rotate(fdfb_ctx *ctx, uint32_t *d_acc, const uint32_t *d_ctN, uint32_t A,
                       uint32_t accs_per_ct, uint32_t flags, void *stream);

@@ -22,6 +22,7 @@ _LIB_PATH = _buildmod.LIB
 
 OUT_EXTRACTED = 0x1
 PLAIN = 0x2
+DIRECT = 0x4
 
 FDFB_OK = 0
 _ERRNAMES = {-1: "FDFB_EINVAL", -2: "FDFB_ENOMEM", -3: "FDFB_EDEVICE", -4: "FDFB_EABORTED",

@@ -428,17 +428,12 @@ int ensure_device(fdfb_ctx &c)
             return rc;
         }
         if (c.mfma_ok) {
-            // FDFB_BR_FORM=direct selects the four-block form (comparison runs)
-            const char *form = std::getenv("FDFB_BR_FORM");
-            c.kara = !(form && std::string(form) == "direct");
-            std::vector<int8_t> fr = c.kara ? build_brk_kara(c) : build_brk_fragments(c);
+            std::vector<int8_t> fr = build_brk_kara(c);
             int8_t *p = nullptr;
             if ((rc = dev_upload(&p, fr.data(), fr.size()))) return rc;
             c.d_brk_frag = p;
-            if (c.kara) {
-                std::vector<uint32_t> corr = build_brk_kara_corr(c);
-                if ((rc = dev_upload(&c.d_brk_corr, corr.data(), corr.size()))) return rc;
-            }
+            std::vector<uint32_t> corr = build_brk_kara_corr(c);
+            if ((rc = dev_upload(&c.d_brk_corr, corr.data(), corr.size()))) return rc;
         }
         c.on_device = true;
     }
@@ -450,6 +445,17 @@ int ensure_device(fdfb_ctx &c)
     return FDFB_OK;
 }
 
+
+int ensure_form(fdfb_ctx &c, uint32_t flags)
+{
+    if ((flags & FDFB_DIRECT) && !c.d_brk_direct) {
+        std::vector<int8_t> fr = build_brk_fragments(c);
+        int8_t *p = nullptr;
+        if (int rc = dev_upload(&p, fr.data(), fr.size())) return rc;
+        c.d_brk_direct = p;
+    }
+    return FDFB_OK;
+}
 
 size_t Scratch::bytes_for(const fdfb_params &P, uint32_t B, uint32_t L)
 {
@@ -499,9 +505,9 @@ namespace fdfbi {
 hipError_t run_br(fdfb_ctx &c, uint32_t *acc, const uint32_t *ctN, uint32_t A, uint32_t per,
                   uint32_t flags, hipStream_t st)
 {
+    if (flags & FDFB_DIRECT) return fdfbk::launch_br_mfma(c.geom, acc, ctN, A, per, c.d_brk_direct, st);
     if (!(flags & FDFB_PLAIN) && c.mfma_ok)
-        return c.kara ? fdfbk::launch_br_kara(c.geom, acc, ctN, A, per, c.d_brk_frag, c.d_brk_corr, st)
-                      : fdfbk::launch_br_mfma(c.geom, acc, ctN, A, per, c.d_brk_frag, st);
+        return fdfbk::launch_br_kara(c.geom, acc, ctN, A, per, c.d_brk_frag, c.d_brk_corr, st);
     return fdfbk::launch_br_plain(c.geom, acc, ctN, A, per, c.d_brk, st);
 }
 
@@ -520,7 +526,11 @@ hipError_t run_ks(fdfb_ctx &c, bool packing, const uint32_t *in, uint32_t B, uin
 // The requested blind-rotation form must exist for the context's parameters.
 int check_form(const fdfb_ctx &c, uint32_t flags)
 {
-    if ((flags & FDFB_PLAIN) ? !plain_br_fits(c.P) : !(c.mfma_ok || plain_br_fits(c.P)))
+    if ((flags & FDFB_PLAIN) && (flags & FDFB_DIRECT))
+        return fail(FDFB_EINVAL, "FDFB_PLAIN and FDFB_DIRECT are exclusive");
+    if ((flags & FDFB_PLAIN) ? !plain_br_fits(c.P)
+        : (flags & FDFB_DIRECT) ? !c.mfma_ok
+        : !(c.mfma_ok || plain_br_fits(c.P)))
         return fail(FDFB_ENOTSUP, "this blind-rotation form does not support the parameter set");
     return FDFB_OK;
 }
@@ -537,6 +547,7 @@ int bootstrap_with(fdfb_ctx &c, Scratch &sc, const uint32_t *d_cts, const int32_
 {
     int rc;
     if ((rc = ensure_device(c))) return rc;
+    if ((rc = ensure_form(c, flags))) return rc;
     if ((rc = ensure_scratch(c, sc, B, L))) return rc;
     const uint32_t E = B * L;  // table evaluations, sample-major: e = b L + l
     const fdfbk::Geometry &G = c.geom;
@@ -633,7 +644,7 @@ int fdfb_bootstrap_batch(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *d_lu
     if (c->abort_flag.load()) return fail(FDFB_EABORTED, "abort flag raised");
     if (B == 0) return FDFB_OK;
     if (!d_cts || !d_lut_ids || !d_out) return fail(FDFB_EINVAL, "null buffer");
-    if (flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+    if (flags & ~kAllFlags) return fail(FDFB_EINVAL, "unknown flag");
     if (int rc = check_form(*c, flags)) return rc;
     return bootstrap_with(*c, c->scratch, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream);
 }
@@ -646,7 +657,7 @@ int fdfb_bootstrap_multi_lut(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *
     if (L == 0) return fail(FDFB_EINVAL, "at least one table per sample");
     if (B == 0) return FDFB_OK;
     if (!d_cts || !d_lut_ids || !d_out) return fail(FDFB_EINVAL, "null buffer");
-    if (flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+    if (flags & ~kAllFlags) return fail(FDFB_EINVAL, "unknown flag");
     if (int rc = check_form(*c, flags)) return rc;
     return bootstrap_with(*c, c->scratch, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream, L);
 }
@@ -658,10 +669,11 @@ int fdfb_tfhe_bootstrap_batch(fdfb_ctx *c, const uint32_t *d_cts, const int32_t 
     if (c->abort_flag.load()) return fail(FDFB_EABORTED, "abort flag raised");
     if (B == 0) return FDFB_OK;
     if (!d_cts || !d_lut_ids || !d_out) return fail(FDFB_EINVAL, "null buffer");
-    if (flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+    if (flags & ~kAllFlags) return fail(FDFB_EINVAL, "unknown flag");
     int rc;
     if ((rc = check_form(*c, flags))) return rc;
     if ((rc = ensure_device(*c))) return rc;
+    if ((rc = ensure_form(*c, flags))) return rc;
     Scratch &sc = c->scratch;
     if ((rc = ensure_scratch(*c, sc, B))) return rc;
     const fdfbk::Geometry &G = c->geom;
@@ -688,7 +700,7 @@ int fdfb_bootstrap_multi(const fdfb_job *jobs, uint32_t njobs, void *stream)
         if (j.ctx->abort_flag.load()) return fail(FDFB_EABORTED, "abort flag raised");
         if (j.B == 0) continue;
         if (!j.d_cts || !j.d_lut_ids || !j.d_out) return fail(FDFB_EINVAL, "null buffer in job");
-        if (j.flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+        if (j.flags & ~kAllFlags) return fail(FDFB_EINVAL, "unknown flag");
         if (int rc = check_form(*j.ctx, j.flags)) return rc;
     }
     // each job's launches already fill the device (measured: running the jobs
@@ -731,8 +743,10 @@ int fdfb_blind_rotate(fdfb_ctx *c, uint32_t *d_acc, const uint32_t *d_ctN, uint3
     if (!c) return fail(FDFB_EINVAL, "null context");
     if (A == 0) return FDFB_OK;
     if (!d_acc || !d_ctN || accs_per_ct == 0) return fail(FDFB_EINVAL, "null buffer or accs_per_ct = 0");
+    if (flags & ~kAllFlags) return fail(FDFB_EINVAL, "unknown flag");
     if (int rc = check_form(*c, flags)) return rc;
     int rc = ensure_device(*c);
+    if (!rc) rc = ensure_form(*c, flags);
     if (rc) return rc;
     K_TRY(run_br(*c, d_acc, d_ctN, A, accs_per_ct, flags, (hipStream_t)stream));
     return FDFB_OK;
@@ -949,7 +963,7 @@ int fdfb_br_launches(fdfb_ctx *c, uint32_t A, uint32_t per_ct, uint32_t flags, u
     if (rc) return rc;
     if ((rc = ensure_device(*c))) return rc;
     *launches = A ? 1 : 0;
-    if (A && !(flags & FDFB_PLAIN) && c->mfma_ok && c->kara)
+    if (A && !(flags & (FDFB_PLAIN | FDFB_DIRECT)) && c->mfma_ok)
         K_TRY(fdfbk::br_kara_launches(c->geom, A, per_ct, launches));
     return FDFB_OK;
 }

@@ -36,12 +36,12 @@ struct fdfb_ctx {
 
     fdfbk::Geometry geom{};
     bool mfma_ok = false;
-    bool kara = false;  // MFMA blind rotation in its Karatsuba form (set at upload)
 
     bool on_device = false;
     uint32_t *d_brk = nullptr, *d_pk = nullptr, *d_ksk = nullptr;
-    void *d_brk_frag = nullptr;
+    void *d_brk_frag = nullptr;      // Karatsuba form: lane-ordered key fragments
     uint32_t *d_brk_corr = nullptr;  // Karatsuba form: offset correction per (i, j)
+    void *d_brk_direct = nullptr;    // direct form (FDFB_DIRECT): key byte planes, built on first use
     void *d_pk_frag = nullptr, *d_ksk_frag = nullptr;  // int8 MFMA key-switch fragments
     int32_t *d_luts = nullptr;
     int dev_nluts = 0;
@@ -57,7 +57,8 @@ struct fdfb_ctx {
     {
         for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
         scratch.release();
-        for (void *p : {(void *)d_brk, (void *)d_pk, (void *)d_ksk, d_brk_frag, (void *)d_brk_corr, d_pk_frag, d_ksk_frag,
+        for (void *p : {(void *)d_brk, (void *)d_pk, (void *)d_ksk, d_brk_frag, (void *)d_brk_corr, d_brk_direct,
+                        d_pk_frag, d_ksk_frag,
                         (void *)d_luts})
             if (p) (void)hipFree(p);
     }
@@ -66,6 +67,10 @@ struct fdfb_ctx {
 namespace fdfbi {
 
 int fail(int code, const std::string &msg);
+// Every flag an entry point accepts.
+constexpr uint32_t kAllFlags = FDFB_OUT_EXTRACTED | FDFB_PLAIN | FDFB_DIRECT;
+// Upload what the requested blind-rotation form needs beyond ensure_device.
+int ensure_form(fdfb_ctx &c, uint32_t flags);
 // Upload keys and registered tables on first use (or after new tables).
 int ensure_device(fdfb_ctx &c);
 int ensure_scratch(fdfb_ctx &c, Scratch &sc, uint32_t B, uint32_t L = 1);

@@ -223,7 +223,7 @@ int fdfb_server_submit(fdfb_server *sv, uint32_t ctx_index, const uint32_t *d_ct
     if (ctx_index >= sv->ctxs.size()) return fail(FDFB_EINVAL, "context index out of range");
     if (B == 0 || B > sv->max_batch) return fail(FDFB_EINVAL, "request size must be in 1..max_batch");
     if (!d_cts || !d_lut_ids || !d_out) return fail(FDFB_EINVAL, "null buffer");
-    if (flags & ~(FDFB_OUT_EXTRACTED | FDFB_PLAIN)) return fail(FDFB_EINVAL, "unknown flag");
+    if (flags & ~fdfbi::kAllFlags) return fail(FDFB_EINVAL, "unknown flag");
     if (int rc = fdfbi::check_form(*sv->ctxs[ctx_index], flags)) return rc;
     if (sv->ctxs[ctx_index]->nluts != sv->ctxs[ctx_index]->dev_nluts)
         return fail(FDFB_EINVAL, "tables must be registered before the server is created");

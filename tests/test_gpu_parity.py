@@ -13,7 +13,7 @@ fd = pytest.importorskip("paper_2109_02731_amd")
 
 pytestmark = pytest.mark.gpu
 M32 = 1 << 32
-FORMS = {"batched": 0, "plain": fd.PLAIN}
+FORMS = {"batched": 0, "plain": fd.PLAIN, "direct": fd.DIRECT}
 
 
 def say(msg):
@@ -290,8 +290,9 @@ def keys_2048():
     return get
 
 
+@pytest.mark.parametrize("form", ["batched", "direct"])
 @pytest.mark.parametrize("name", list(N2048))
-def test_blind_rotate_n2048(keys_2048, name):
+def test_blind_rotate_n2048(keys_2048, name, form):
     ctx, ok = keys_2048(name)
     p = N2048[name]
     N = p.N
@@ -299,9 +300,9 @@ def test_blind_rotate_n2048(keys_2048, name):
     A, per = 6, 2
     acc = u32(g, A, 2 * N)
     ctN = g.integers(0, 2 * N, (A // per, p.n + 1)).astype(np.uint32)
-    say(f"blind_rotate {name} batched A={A}")
+    say(f"blind_rotate {name} {form} A={A}")
     d_acc = fd.to_device(acc)
-    ctx.blind_rotate(d_acc, fd.to_device(ctN), per, 0)
+    ctx.blind_rotate(d_acc, fd.to_device(ctN), per, FORMS[form])
     torch.cuda.synchronize()
     got = fd.to_host(d_acc)
     refs = run_oracle_many(lambda a: oracle.blind_rotate(p, ok.brk, ctN[a // per], acc[a]), A)
@@ -336,8 +337,11 @@ def test_br_launch_count(c2):
     many = ctx.br_launches(1 << 16, 2)
     assert many >= 2
     assert ctx.br_launches(1 << 16, 2, flags=fd.PLAIN) == 1
+    assert ctx.br_launches(1 << 16, 2, flags=fd.DIRECT) == 1
     with pytest.raises(fd.FdfbError):
         ctx.br_launches(4, 0)
+    with pytest.raises(fd.FdfbError):
+        ctx.br_launches(4, 2, flags=fd.PLAIN | fd.DIRECT)
 
 
 @pytest.mark.parametrize("flags", [0, fd.OUT_EXTRACTED])
