@@ -22,7 +22,7 @@
  *    context must not overlap from several threads; distinct contexts are
  *    independent.
  *  - Results are bit-identical for identical inputs whatever the batch size,
- *    batch composition, kernel form (batched or plain) or stream.
+ *    batch composition, kernel form (Karatsuba, direct or plain) or stream.
  */
 #ifndef FDFB_H
 #define FDFB_H

@@ -407,7 +407,8 @@ __global__ __launch_bounds__(256) void k_br_plain(uint32_t *__restrict__ acc_g,
 }
 
 // ---------------------------------------------------------------------------
-// Batched blind rotation on int8 MFMA.
+// Batched blind rotation on int8 MFMA, direct form (FDFB_DIRECT; the default
+// is the Karatsuba form k_br_kara below).
 //
 // One workgroup owns one accumulator for the whole loop over i (the CMux
 // chain is sequential in i, independent across accumulators); its
@@ -421,9 +422,10 @@ __global__ __launch_bounds__(256) void k_br_plain(uint32_t *__restrict__ acc_g,
 // (D~[x - N] = -D[x]) and the 16 columns are col = s*4 + l:
 //   s in 0..3   key shifted by 16 s, so one A tile of 16 rows yields 64 rows,
 //   l in 0..3   balanced signed byte limb of the 32-bit key word.
-// B fragments are precomputed on the host (one 1 KB lane-ordered block per
-// (i, r, k-block, j)) and double-buffered in registers: the next row's block
-// is in flight while the current row runs.  A fragments are windows of a
+// B fragments come from key byte planes built on the host (per (i, r, j) one
+// plane per limb of the negacyclic extension; lane (s, l, g) reads 16
+// aligned bytes of plane l) and are double-buffered in registers: the next
+// unit's fragments are in flight while the current unit runs.  A fragments are windows of a
 // reversed copy of D~ in LDS, aligned per lane with v_alignbyte; a Toeplitz
 // fragment depends only on the diagonal m0 - p0, so each one is built once
 // per diagonal and used for every tile on it.  Each wavefront writes the
