@@ -118,6 +118,8 @@ int fdfb_register_lut(fdfb_ctx *ctx, const uint32_t *table, int32_t *lut_id);
  *              cannot hold the parameter set, e.g. N = 2048 with ell = 4)
  * Scratch memory is taken from a pool owned by the context and grown on
  * demand (hipMalloc) the first time a larger B is seen.  B = 0 is a no-op.
+ * After one call with at least this B (keys uploaded, scratch sized), the
+ * call enqueues kernels only and can be captured into a HIP graph.
  * Errors: FDFB_EINVAL (null pointer with B > 0), FDFB_ENOMEM, FDFB_EDEVICE.
  * lut_ids are validated on the device: an out-of-range id yields all-zero
  * output for that sample.
