@@ -114,14 +114,18 @@ struct fdfb_server {
             bool any_busy = false;
             for (Slot &s : slots) {
                 if (!s.busy) continue;
-                if (hipEventQuery(s.done) != hipSuccess) {
+                const hipError_t q = hipEventQuery(s.done);
+                if (q == hipErrorNotReady) {
                     any_busy = true;
                     continue;
                 }
+                // hipSuccess: the batch is done; any other result is a device
+                // error: its requests fail instead of waiting forever
+                if (q != hipSuccess) fatal = FDFB_EDEVICE;
                 const auto now = Clock::now();
                 for (uint64_t id : s.reqs) {
                     Request &r = reqs[id];
-                    if (r.status == 0) r.status = 1;
+                    if (r.status == 0) r.status = (q == hipSuccess) ? 1 : FDFB_EDEVICE;
                     r.t_done = now;
                     stats.requests_done++;
                     stats.bootstraps_done += r.B;
