@@ -253,6 +253,34 @@ def tfhe_bench(fd, torch, ctx, d_cts, d_ids, B: int, steps: int, fdfb_ms: float)
             "note": "half-domain only (m < t/2); FDFB's time over this is the price of the full domain"}
 
 
+def config_sweep(fd, torch, W, B: int, steps: int):
+    """bootstraps/s of every parameter preset at batch B (schoolbook int8
+    work of the blind rotations over the measured time, as for the headline)."""
+    res = {}
+    for name, p in W.PRESETS.items():
+        ctx = fd.Context.keygen(p, W.KEY_SEED[name])
+        lut = W.random_lut(W.LUT_SEED[name], p.t)
+        lid = ctx.register_lut(lut)
+        msgs = W.messages(W.MSG_SEED[name], B, p.t)
+        cts = fd.to_device(ctx.encrypt_debug(msgs, seed=W.MSG_SEED[name]))
+        ids = torch.full((B,), lid, dtype=torch.int32, device="cuda")
+        out = torch.empty((B, p.n + 1), dtype=torch.int32, device="cuda")
+        ctx.bootstrap_batch(cts, ids, out)
+        torch.cuda.synchronize()
+        ok = bool(np.array_equal(ctx.decrypt_debug(fd.to_host(out))[0], lut[msgs]))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.bootstrap_batch(cts, ids, out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ops = br_ops_per_accumulator(p) * B * (p.boot_ell + 1)
+        res[name] = {"n": p.n, "N": p.N, "t": p.t, "blind_rotations_per_bootstrap": p.boot_ell + 1,
+                     "bootstraps_per_s": B / dt, "ms_per_batch": dt * 1e3, "correct": ok,
+                     "schoolbook_int8_tops": ops / dt / 1e12}
+        print(f"[bench] {name}: {B / dt:.0f} bootstraps/s", file=sys.stderr, flush=True)
+    return {"batch": B, "steps": steps, "presets": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +299,8 @@ def main():
                     help="also time the direct (non-Karatsuba) MFMA form this many steps (0 skips)")
     ap.add_argument("--tfhe-steps", type=int, default=5,
                     help="also time the one-rotation TFHE-style bootstrap this many steps (0 skips)")
+    ap.add_argument("--config-sweep", type=int, default=0, metavar="STEPS",
+                    help="also time every parameter preset at batch 1024 this many steps (0 skips)")
     ap.add_argument("--mixed-steps", type=int, default=0,
                     help="also time the uneven two-degree batch (one multi-job submission) this many times")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -397,6 +427,10 @@ def main():
         print("[bench] TFHE-style yardstick", file=sys.stderr, flush=True)
         tfhe = tfhe_bench(fd, torch, ctx, d_cts, d_ids, B, args.tfhe_steps, wall / K * 1e3)
 
+    sweep = None
+    if args.config_sweep > 0:
+        sweep = config_sweep(fd, torch, W, B, args.config_sweep)
+
     mixed = None
     if args.mixed_steps > 0:
         print("[bench] uneven two-degree batch", file=sys.stderr, flush=True)
@@ -442,6 +476,7 @@ def main():
         "tfhe_yardstick": tfhe,
         "direct_form": direct,
         "mixed": mixed,
+        "config_sweep": sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
