@@ -944,6 +944,235 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
 }
 
 // ---------------------------------------------------------------------------
+// One-wavefront form of k_br_kara for N <= 1024: a single wavefront owns the
+// accumulator and computes both output components, so each Toeplitz A
+// fragment feeds the MFMAs of both components and no workgroup barrier is
+// needed (all LDS traffic of an accumulator is in one wavefront's program
+// order).  Same digits, products, layouts and results as k_br_kara.
+// ---------------------------------------------------------------------------
+template <int N, int ELL, int CH>
+__global__ __launch_bounds__(64, 1) void k_br_kara1w(uint32_t *__restrict__ acc_g,
+                                                    const uint32_t *__restrict__ ctN,
+                                                    uint32_t accs_per_ct, int n,
+                                                    const v4i *__restrict__ bfrag,
+                                                    const uint32_t *__restrict__ corr, int log2B)
+{
+    using G = BrKara<N, ELL, CH>;
+    static_assert(G::WPC == 1, "one wavefront per accumulator needs N <= 1024");
+    constexpr int M = G::M;
+    extern __shared__ uint8_t smem[];
+    uint32_t *accL = (uint32_t *)smem;  // [2][N]: per component, even half then odd half
+    uint32_t *digL = accL + 2 * N;      // [RV][3 products][SEQ_WORDS]
+    auto seq = [&](int r, int p) { return digL + (r * 3 + p) * G::SEQ_WORDS; };
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t a_idx = blockIdx.x;
+    uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
+    for (int x = lane; x < 2 * N; x += 64) {
+        const int m = x & (N - 1);
+        accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)] = row[x];
+    }
+    const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
+    const uint32_t drop = 32 - ELL * log2B;
+    const int ri = lane & 15, g = lane >> 4;
+    const int S0 = M - 4 * ri + 16 * g;
+    const int limb = lane & 3, ss = (lane >> 2) & 3;
+    // B fragments of unit (row r, product p, chunk c), component 0; component 1 follows
+    auto frag = [&](int i, int r, int p, int c) {
+        return bfrag + (((((size_t)i * G::RV + r) * 3 + p) * 2) * G::NKB + c * G::KC) * 64 + lane;
+    };
+    constexpr int JSTRIDE = G::NKB * 64;
+    auto next_live = [&](int i) {
+        int k = i + 1;
+        while (k < n && __builtin_amdgcn_readfirstlane(crow[k]) == 0) ++k;
+        return k;
+    };
+
+    int i = next_live(-1);
+    v4i B0[2][G::KC], B1[2][G::KC];
+    {
+        const v4i *bp = frag(i < n ? i : 0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int kb = 0; kb < G::KC; ++kb) B0[j][kb] = bp[j * JSTRIDE + kb * 64];
+    }
+    __syncthreads();
+    while (i < n) {
+        const uint32_t a = __builtin_amdgcn_readfirstlane(crow[i]);
+        const int inext = next_live(i);
+
+        // digits of (X^{-a} acc_c - acc_c) for both components, as in k_br_kara
+        {
+            const uint32_t al = a >> 1, odd_a = a & 1;
+#pragma unroll
+            for (int jc = 0; jc < 2; ++jc) {
+                const uint32_t *accJ = accL + jc * N;
+                const uint4 *srcE = (const uint4 *)(accJ + (odd_a ? M : 0));
+                const uint4 *srcO = (const uint4 *)(accJ + (odd_a ? 0 : M));
+                const uint4 *ownE = (const uint4 *)accJ, *ownO = (const uint4 *)(accJ + M);
+#pragma unroll
+                for (int qq = 0; qq < (G::QPW + 63) / 64; ++qq) {
+                    if (G::QPW % 64 != 0 && qq * 64 + lane >= G::QPW) break;
+                    const uint32_t q = qq * 64 + lane;
+                    uint32_t rE[4], rO[4];
+                    kara_rot4<M>(srcE, q, al, rE);
+                    kara_rot4<M>(srcO, q, al + odd_a, rO);
+                    const uint4 E4 = ownE[q], O4 = ownO[q];
+                    const uint32_t oE[4] = {E4.x, E4.y, E4.z, E4.w}, oO[4] = {O4.x, O4.y, O4.z, O4.w};
+                    uint32_t tE[4], tO[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t dE = rE[u] - oE[u], dO = rO[u] - oO[u];
+                        tE[u] = drop ? (dE + (1u << (drop - 1))) >> drop : dE;
+                        tO[u] = drop ? (dO + (1u << (drop - 1))) >> drop : dO;
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < ELL; ++jj) {
+#pragma unroll
+                        for (int h = 0; h < CH; ++h) {
+                            const uint32_t off = log2B * jj + 7 * h;
+                            const bool full = 7 * (h + 1) <= log2B;
+                            const uint32_t wdt = full ? 7u : (uint32_t)log2B - 7 * h;
+                            const uint32_t oe = full ? 64u : 0u, oo = full ? 63u : 0u;
+                            const uint32_t cE = (128u - oe) * 0x01010101u, nE = (128u + oe) * 0x01010101u;
+                            const uint32_t cO = (128u - oo) * 0x01010101u, nO = (128u + oo) * 0x01010101u;
+                            const uint32_t cS = (128u - oe - oo) * 0x01010101u, nS = (128u + oe + oo) * 0x01010101u;
+                            uint32_t pe = __builtin_amdgcn_ubfe(tE[3], off, wdt);
+                            pe |= __builtin_amdgcn_ubfe(tE[2], off, wdt) << 8;
+                            pe |= __builtin_amdgcn_ubfe(tE[1], off, wdt) << 16;
+                            pe |= __builtin_amdgcn_ubfe(tE[0], off, wdt) << 24;
+                            uint32_t po = __builtin_amdgcn_ubfe(tO[3], off, wdt);
+                            po |= __builtin_amdgcn_ubfe(tO[2], off, wdt) << 8;
+                            po |= __builtin_amdgcn_ubfe(tO[1], off, wdt) << 16;
+                            po |= __builtin_amdgcn_ubfe(tO[0], off, wdt) << 24;
+                            const uint32_t ps = pe + po;
+                            const int r = jc * G::RPC + jj * CH + h;
+                            uint32_t *sE = seq(r, 0), *sO = seq(r, 1), *sS = seq(r, 2);
+                            sE[M / 4 - q - 1] = (pe + cE) ^ 0x80808080u;
+                            sE[M / 2 - q - 1] = (nE - pe) ^ 0x80808080u;
+                            sO[M / 4 - q - 1] = (po + cO) ^ 0x80808080u;
+                            sO[M / 2 - q - 1] = (nO - po) ^ 0x80808080u;
+                            sS[M / 4 - q - 1] = (ps + cS) ^ 0x80808080u;
+                            sS[M / 2 - q - 1] = (nS - ps) ^ 0x80808080u;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();  // one wavefront: orders the digit writes before the fragment reads
+
+        v4i C[3][2][G::NT];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int t = 0; t < G::NT; ++t) C[p][j][t] = v4i{0, 0, 0, 0};
+
+        auto one_unit = [&](const int r, auto P_, const int c, v4i(&Bc)[2][G::KC], v4i(&Bn)[2][G::KC],
+                            const v4i *np) {
+            constexpr int p = decltype(P_)::value;
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int kb = 0; kb < G::KC; ++kb) Bn[j][kb] = np[j * JSTRIDE + kb * 64];
+            __builtin_amdgcn_sched_barrier(0);
+            const int dshift = -64 * c * G::KC;
+            const uint32_t *ab = seq(r, p) + (S0 - dshift - G::DLOC) / 4;
+            auto afrag = [&](const int dd, v4i &A) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) A[k] = (int)ab[16 * dd + k];
+            };
+            v4i Af[2];
+            afrag(0, Af[0]);
+#pragma unroll
+            for (int dd = 0; dd < G::NDIAG; ++dd) {
+                const int dl = G::DLOC - 64 * dd;
+                if (dd + 1 < G::NDIAG) afrag(dd + 1, Af[(dd + 1) & 1]);
+#pragma unroll
+                for (int kb = 0; kb < G::KC; ++kb) {
+                    const int m0 = dl + 64 * kb;
+                    if (m0 >= 0 && m0 <= 64 * (G::NT - 1)) {
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            C[p][j][m0 / 64] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Af[dd & 1], Bc[j][kb],
+                                                                                    C[p][j][m0 / 64], 0, 0, 0);
+                    }
+                }
+            }
+        };
+
+#pragma unroll 1
+        for (int r = 0; r < G::RV; r += G::RSTEP) {
+            StaticFor<0, G::USTEP>::run([&](auto U_) {
+                constexpr int u = decltype(U_)::value;
+                constexpr int rr = u / G::UPR, p = (u % G::UPR) / G::NCH, c = u % G::NCH;
+                const v4i *np;
+                if constexpr (u + 1 < G::USTEP) {
+                    constexpr int u2 = u + 1;
+                    np = frag(i, r + u2 / G::UPR, (u2 % G::UPR) / G::NCH, u2 % G::NCH);
+                } else {
+                    np = (r + G::RSTEP < G::RV) ? frag(i, r + G::RSTEP, 0, 0)
+                                                : frag(inext < n ? inext : i, 0, 0, 0);
+                }
+                if constexpr (u % 2 == 0) one_unit(r + rr, IC<p>{}, c, B0, B1, np);
+                else one_unit(r + rr, IC<p>{}, c, B1, B0, np);
+            });
+        }
+
+        // recombine both components (reduce-scatter over the lane quad) and add
+        // the offset correction of this step
+        const bool p1 = lane & 1, h1 = lane & 2;
+        auto rs = [&](const uint32_t (&z)[4]) -> uint32_t {
+            const uint32_t y0 = z[0] << (8 * limb), y1 = z[1] << (8 * limb);
+            const uint32_t y2 = z[2] << (8 * limb), y3 = z[3] << (8 * limb);
+            const uint32_t za = (p1 ? y1 : y0) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(p1 ? y0 : y1), 0xB1, 0xF, 0xF, false);
+            const uint32_t zb = (p1 ? y3 : y2) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(p1 ? y2 : y3), 0xB1, 0xF, 0xF, false);
+            return (h1 ? zb : za) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(h1 ? za : zb), 0x4E, 0xF, 0xF, false);
+        };
+        const int mb = 16 * g + 4 * limb + ss - 1;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            uint32_t *accE = accL + j * N, *accO = accE + M;
+            const uint32_t *cp = corr + ((size_t)i * 2 + j) * N;
+#pragma unroll
+            for (int t = 0; t < G::NT; ++t) {
+                const int m = 64 * t + mb;
+                const int mc = m & (M - 1);
+                const uint32_t wE = cp[mc], wO = cp[M + mc];
+                uint32_t zo[4], z1[4], z2[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    z1[v] = (uint32_t)C[0][j][t][v];
+                    z2[v] = (uint32_t)C[1][j][t][v];
+                    zo[v] = (uint32_t)C[2][j][t][v] - z1[v] - z2[v];
+                }
+                const uint32_t xo = rs(zo), x1 = rs(z1), x2 = rs(z2);
+                // LDS atomic adds: lanes of one instruction touch distinct words,
+                // but later statements touch words of other lanes (m + 1), which
+                // plain read-modify-writes could reorder
+                if (t == 0 && mb < 0) {
+                    atomicAdd(&accO[M - 1], wO - xo);  // coefficient -1 is -(coefficient M - 1)
+                    atomicAdd(&accE[M - 1], wE - x1);
+                } else {
+                    atomicAdd(&accO[m], xo + wO);
+                    atomicAdd(&accE[m], x1 + wE);
+                }
+                atomicAdd(&accE[m + 1], x2);  // Y P_o
+            }
+        }
+        __syncthreads();  // the accumulate completes before the next digits read it
+        i = inext;
+    }
+    __syncthreads();
+    for (int x = lane; x < 2 * N; x += 64) {
+        const int m = x & (N - 1);
+        row[x] = accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static int ilog2i(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
@@ -1086,21 +1315,35 @@ static hipError_t launch_br_mfma_t(const Geometry &G, uint32_t *acc, const uint3
     X(2048, 2, 2)             \
     X(2048, 4, 1)
 
-// Workgroups of k_br_kara resident on the whole device at once.
+// The blind-rotation kernel of the Karatsuba form for (N, ell, CH): one
+// wavefront per accumulator for N <= 1024, else two per output component.
+template <int N, int ELL, int CH>
+static const void *br_kara_kernel()
+{
+    if constexpr (BrKara<N, ELL, CH>::WPC == 1) return (const void *)k_br_kara1w<N, ELL, CH>;
+    else return (const void *)k_br_kara<N, ELL, CH>;
+}
+template <int N, int ELL, int CH>
+static constexpr int br_kara_threads()
+{
+    return BrKara<N, ELL, CH>::WPC == 1 ? 64 : 64 * BrKara<N, ELL, CH>::WAVES;
+}
+
+// Workgroups of the Karatsuba blind rotation resident on the whole device at once.
 template <int N, int ELL, int CH>
 static hipError_t br_kara_capacity(uint32_t *cap_out)
 {
     using GK = BrKara<N, ELL, CH>;
     static uint32_t cap = 0;
     if (!cap) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_br_kara<N, ELL, CH>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)GK::LDS_BYTES);
+        hipError_t e = hipFuncSetAttribute(br_kara_kernel<N, ELL, CH>(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)GK::LDS_BYTES);
         int dev = 0, cus = 0, per_cu = 0;
         if (e == hipSuccess) e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_br_kara<N, ELL, CH>,
-                                                             64 * GK::WAVES, GK::LDS_BYTES);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, br_kara_kernel<N, ELL, CH>(),
+                                                             br_kara_threads<N, ELL, CH>(), GK::LDS_BYTES);
         if (e != hipSuccess) return e;
         cap = (uint32_t)std::max(1, per_cu * cus);
     }
@@ -1114,13 +1357,6 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
                                    hipStream_t s)
 {
     using GK = BrKara<N, ELL, CH>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_br_kara<N, ELL, CH>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)GK::LDS_BYTES);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
     // Launch in rounds of the resident capacity (whole ciphertexts): the
     // workgroups of one launch start together and walk the key in step, so a
     // key block is fetched into each XCD's L2 once and shared, where a second
@@ -1131,9 +1367,14 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
     const uint32_t chunk = std::max(accs_per_ct, cap / accs_per_ct * accs_per_ct);
     for (uint32_t a0 = 0; a0 < A; a0 += chunk) {
         const uint32_t cnt = std::min(chunk, A - a0);
-        hipLaunchKernelGGL((k_br_kara<N, ELL, CH>), dim3(cnt), dim3(64 * GK::WAVES), GK::LDS_BYTES, s,
-                           acc + (size_t)a0 * 2 * N, ctN + (size_t)(a0 / accs_per_ct) * (G.n + 1), accs_per_ct,
-                           G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+        uint32_t *acc_c = acc + (size_t)a0 * 2 * N;
+        const uint32_t *ct_c = ctN + (size_t)(a0 / accs_per_ct) * (G.n + 1);
+        if constexpr (GK::WPC == 1)
+            hipLaunchKernelGGL((k_br_kara1w<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS_BYTES, s, acc_c, ct_c,
+                               accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+        else
+            hipLaunchKernelGGL((k_br_kara<N, ELL, CH>), dim3(cnt), dim3(64 * GK::WAVES), GK::LDS_BYTES, s, acc_c,
+                               ct_c, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
