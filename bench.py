@@ -387,7 +387,7 @@ def main():
     traffic = load_traffic(units_per_step)
     executed = achieved * 0.75  # one Karatsuba level: 3 half-size products for 4
     launches = ctx.br_launches(B * p.boot_ell, p.boot_ell) + ctx.br_launches(B, 1)
-    roofline = {"bound": "mfma", "kernel": "k_br_kara<1024,3,1>", "achieved": achieved,
+    roofline = {"bound": "mfma", "kernel": "k_br_kara1w<1024,3,1>", "achieved": achieved,
                 "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_INT8_TOPS,
                 "traffic": traffic,
                 "ops_per_launch_avg": ops / launches, "avg_launch_ms": br_ms / launches,
