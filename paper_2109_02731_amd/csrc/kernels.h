@@ -36,7 +36,7 @@ hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN,
 hipError_t launch_br_kara(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
                           uint32_t accs_per_ct, const void *brk_frag, const uint32_t *corr, hipStream_t s);
 // Kernel launches launch_br_kara issues for A accumulators (rounds of the
-// device's resident capacity, whole ciphertexts of accs_per_ct).
+// device's resident capacity; a round may begin inside a sample's accumulators).
 hipError_t br_kara_launches(const Geometry &G, uint32_t A, uint32_t accs_per_ct, uint32_t *launches);
 // add_base != 0: sample b of accumulator a gets add_base * L_boot^(a % per) added.
 hipError_t launch_extract(const Geometry &G, const uint32_t *acc, uint32_t A, uint32_t per,

@@ -715,7 +715,7 @@ __device__ __attribute__((always_inline)) inline void kara_rot4(const uint4 *src
 
 template <int N, int ELL, int CH>
 __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g,
-                                                    const uint32_t *__restrict__ ctN,
+                                                    const uint32_t *__restrict__ ctN, uint32_t a_base,
                                                     uint32_t accs_per_ct, int n,
                                                     const v4i *__restrict__ bfrag,
                                                     const uint32_t *__restrict__ corr, int log2B)
@@ -731,7 +731,7 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int jc = wv / G::WPC;  // output component of this wavefront
     const int hw = wv % G::WPC;  // its half of the tiles / coefficients
-    const uint32_t a_idx = blockIdx.x;
+    const uint32_t a_idx = a_base + blockIdx.x;  // accumulator; sample a_idx / accs_per_ct
     uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
     for (int x = threadIdx.x; x < 2 * N; x += 64 * G::WAVES) {
         const int m = x & (N - 1);
@@ -952,7 +952,7 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
 // ---------------------------------------------------------------------------
 template <int N, int ELL, int CH>
 __global__ __launch_bounds__(64, 1) void k_br_kara1w(uint32_t *__restrict__ acc_g,
-                                                    const uint32_t *__restrict__ ctN,
+                                                    const uint32_t *__restrict__ ctN, uint32_t a_base,
                                                     uint32_t accs_per_ct, int n,
                                                     const v4i *__restrict__ bfrag,
                                                     const uint32_t *__restrict__ corr, int log2B)
@@ -966,7 +966,7 @@ __global__ __launch_bounds__(64, 1) void k_br_kara1w(uint32_t *__restrict__ acc_
     auto seq = [&](int r, int p) { return digL + (r * 3 + p) * G::SEQ_WORDS; };
 
     const int lane = threadIdx.x & 63;
-    const uint32_t a_idx = blockIdx.x;
+    const uint32_t a_idx = a_base + blockIdx.x;  // accumulator; sample a_idx / accs_per_ct
     uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
     for (int x = lane; x < 2 * N; x += 64) {
         const int m = x & (N - 1);
@@ -1357,24 +1357,22 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
                                    hipStream_t s)
 {
     using GK = BrKara<N, ELL, CH>;
-    // Launch in rounds of the resident capacity (whole ciphertexts): the
-    // workgroups of one launch start together and walk the key in step, so a
-    // key block is fetched into each XCD's L2 once and shared, where a second
-    // round started by completions would drift and re-fetch.
+    // Launch in rounds of the resident capacity: the workgroups of one launch
+    // start together and walk the key in step, so a key block is fetched into
+    // each XCD's L2 once and shared, where a second round started by
+    // completions would drift and re-fetch.  A round may begin inside a
+    // sample's group of accumulators (a_base), so no round is left short.
     uint32_t cap = 0;
     hipError_t e0 = br_kara_capacity<N, ELL, CH>(&cap);
     if (e0 != hipSuccess) return e0;
-    const uint32_t chunk = std::max(accs_per_ct, cap / accs_per_ct * accs_per_ct);
-    for (uint32_t a0 = 0; a0 < A; a0 += chunk) {
-        const uint32_t cnt = std::min(chunk, A - a0);
-        uint32_t *acc_c = acc + (size_t)a0 * 2 * N;
-        const uint32_t *ct_c = ctN + (size_t)(a0 / accs_per_ct) * (G.n + 1);
+    for (uint32_t a0 = 0; a0 < A; a0 += cap) {
+        const uint32_t cnt = std::min(cap, A - a0);
         if constexpr (GK::WPC == 1)
-            hipLaunchKernelGGL((k_br_kara1w<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS_BYTES, s, acc_c, ct_c,
+            hipLaunchKernelGGL((k_br_kara1w<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS_BYTES, s, acc, ctN, a0,
                                accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
         else
-            hipLaunchKernelGGL((k_br_kara<N, ELL, CH>), dim3(cnt), dim3(64 * GK::WAVES), GK::LDS_BYTES, s, acc_c,
-                               ct_c, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+            hipLaunchKernelGGL((k_br_kara<N, ELL, CH>), dim3(cnt), dim3(64 * GK::WAVES), GK::LDS_BYTES, s, acc,
+                               ctN, a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1414,8 +1412,7 @@ hipError_t br_kara_launches(const Geometry &G, uint32_t A, uint32_t accs_per_ct,
     FDFB_BR_MFMA_CASES(X)
 #undef X
     if (e != hipSuccess) return e;
-    const uint32_t chunk = std::max(accs_per_ct, cap / accs_per_ct * accs_per_ct);
-    *launches = (A + chunk - 1) / chunk;
+    *launches = (A + cap - 1) / cap;
     return hipSuccess;
 }
 

@@ -310,6 +310,50 @@ def test_blind_rotate_n2048(keys_2048, name, form):
         assert np.array_equal(got[a], refs[a]), a
 
 
+def _resident_capacity(ctx):
+    """Accumulators one launch of the batched form holds (largest A taking
+    one launch), found from the launch count alone."""
+    lo, hi = 1, 1 << 22
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if ctx.br_launches(mid, 1) == 1:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+def test_blind_rotate_rounds_split_samples(keys_2048):
+    """Three accumulators per sample over more than one launch round: a round
+    may begin inside a sample's group, so every accumulator must still read
+    its own sample's row.  Every accumulator equals the rotation with the row
+    repeated per accumulator (one per sample); the ones at each round
+    boundary match the oracle bit for bit."""
+    ctx, ok = keys_2048("C3B")
+    p = W.C3B
+    N = p.N
+    cap = _resident_capacity(ctx)
+    per = 3
+    A = per * (cap // per + 2)
+    assert ctx.br_launches(A, per) == ctx.br_launches(A, 1) == (A + cap - 1) // cap >= 2
+    g = np.random.default_rng(37)
+    acc = u32(g, A, 2 * N)
+    ctN = g.integers(0, 2 * N, (A // per, p.n + 1)).astype(np.uint32)
+    say(f"blind_rotate C3B rounds A={A} cap={cap}")
+    d_acc = fd.to_device(acc)
+    ctx.blind_rotate(d_acc, fd.to_device(ctN), per, 0)
+    d_rep = fd.to_device(acc)
+    ctx.blind_rotate(d_rep, fd.to_device(np.repeat(ctN, per, axis=0)), 1, 0)
+    torch.cuda.synchronize()
+    got, rep = fd.to_host(d_acc), fd.to_host(d_rep)
+    assert np.array_equal(got, rep)
+    picks = sorted({0, cap - 2, cap - 1, cap, cap + 1, A - 1})
+    refs = run_oracle_many(lambda k: oracle.blind_rotate(p, ok.brk, ctN[picks[k] // per], acc[picks[k]]),
+                           len(picks))
+    for k, a in enumerate(picks):
+        assert np.array_equal(got[a], refs[k]), a
+
+
 def test_fdfb_n2048_vs_oracle(keys_2048):
     ctx, ok = keys_2048("C3B")
     p = W.C3B
@@ -328,14 +372,18 @@ def test_fdfb_n2048_vs_oracle(keys_2048):
 
 
 def test_br_launch_count(c2):
-    """The batched form runs in rounds of the resident capacity (whole
-    ciphertexts); the plain form in one launch; nothing for no accumulators."""
+    """The batched form runs in rounds of the resident capacity (a round may
+    split a sample's accumulators, so the count does not depend on how many
+    each sample has); the plain form in one launch; nothing for no
+    accumulators."""
     ctx = c2[0]
     assert ctx.br_launches(0, 2) == 0
     one = ctx.br_launches(2, 2)
     assert one == 1
     many = ctx.br_launches(1 << 16, 2)
     assert many >= 2
+    for A in (1, 999, 1000, 4097, 1 << 16):
+        assert len({ctx.br_launches(A, per) for per in (1, 2, 3, 5)}) == 1, A
     assert ctx.br_launches(1 << 16, 2, flags=fd.PLAIN) == 1
     assert ctx.br_launches(1 << 16, 2, flags=fd.DIRECT) == 1
     with pytest.raises(fd.FdfbError):
