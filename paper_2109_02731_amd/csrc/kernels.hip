@@ -688,6 +688,8 @@ struct BrKara {
     static constexpr int SEQ_WORDS = M / 2;           // one reversed extension: 2M bytes
     static constexpr int DSETS = 1;                   // one digit set: a barrier follows the accumulate
     static constexpr size_t LDS_BYTES = 4 * (2 * (size_t)N + (size_t)DSETS * RV * 3 * SEQ_WORDS);
+    // k_br_kara1w2: rows of V_e and V_o only (V_e + V_o overwrites V_e after P_e)
+    static constexpr size_t LDS2W_BYTES = 4 * (2 * (size_t)N + (size_t)RV * 2 * SEQ_WORDS);
     static constexpr int QPW = M / 4 / WPC;           // coefficient quads per wavefront and half
     static_assert(RV % RSTEP == 0 && USTEP % 2 == 0, "unit sequence must alternate evenly");
 };
@@ -1173,6 +1175,253 @@ __global__ __launch_bounds__(64, 1) void k_br_kara1w(uint32_t *__restrict__ acc_
 }
 
 // ---------------------------------------------------------------------------
+// k_br_kara1w with two wavefronts per SIMD, for rounds that fill the device:
+// the three products run one after another and are folded into the
+// accumulator in turn, so that registers (one product's tiles) and LDS (two
+// digit sequences per row, V_e + V_o written over V_e once P_e is done) leave
+// room for a second wavefront, whose MFMAs run while the first computes
+// digits or waits.  A round that does not fill every SIMD twice uses
+// k_br_kara1w instead: its register use allows one wavefront per SIMD, so the
+// dispatcher cannot stack two on one SIMD while another idles.  Same digits,
+// products and results as k_br_kara1w.
+// ---------------------------------------------------------------------------
+template <int N, int ELL, int CH>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_br_kara1w2(uint32_t *__restrict__ acc_g,
+                                                    const uint32_t *__restrict__ ctN, uint32_t a_base,
+                                                    uint32_t accs_per_ct, int n,
+                                                    const v4i *__restrict__ bfrag,
+                                                    const uint32_t *__restrict__ corr, int log2B)
+{
+    using G = BrKara<N, ELL, CH>;
+    static_assert(G::WPC == 1, "one wavefront per accumulator needs N <= 1024");
+    constexpr int M = G::M;
+    extern __shared__ uint8_t smem[];
+    uint32_t *accL = (uint32_t *)smem;  // [2][N]: per component, even half then odd half
+    uint32_t *digL = accL + 2 * N;      // [RV][V_e (then V_e + V_o), V_o][SEQ_WORDS]
+    auto seq = [&](int r, int p) { return digL + (r * 2 + (p & 1)) * G::SEQ_WORDS; };
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t a_idx = a_base + blockIdx.x;  // accumulator; sample a_idx / accs_per_ct
+    uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
+    for (int x = lane; x < 2 * N; x += 64) {
+        const int m = x & (N - 1);
+        accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)] = row[x];
+    }
+    const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
+    const uint32_t drop = 32 - ELL * log2B;
+    const int ri = lane & 15, g = lane >> 4;
+    const int S0 = M - 4 * ri + 16 * g;
+    const int limb = lane & 3, ss = (lane >> 2) & 3;
+    // B fragments of unit (row r, product p, chunk c), component 0; component 1 follows
+    auto frag = [&](int i, int r, int p, int c) {
+        return bfrag + (((((size_t)i * G::RV + r) * 3 + p) * 2) * G::NKB + c * G::KC) * 64 + lane;
+    };
+    constexpr int JSTRIDE = G::NKB * 64;
+    auto next_live = [&](int i) {
+        int k = i + 1;
+        while (k < n && __builtin_amdgcn_readfirstlane(crow[k]) == 0) ++k;
+        return k;
+    };
+
+    int i = next_live(-1);
+    v4i B0[2][G::KC], B1[2][G::KC];
+    {
+        const v4i *bp = frag(i < n ? i : 0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int kb = 0; kb < G::KC; ++kb) B0[j][kb] = bp[j * JSTRIDE + kb * 64];
+    }
+    __syncthreads();
+    while (i < n) {
+        const uint32_t a = __builtin_amdgcn_readfirstlane(crow[i]);
+        const int inext = next_live(i);
+
+        // digits of (X^{-a} acc_c - acc_c) for both components, as in k_br_kara
+        {
+            const uint32_t al = a >> 1, odd_a = a & 1;
+#pragma unroll
+            for (int jc = 0; jc < 2; ++jc) {
+                const uint32_t *accJ = accL + jc * N;
+                const uint4 *srcE = (const uint4 *)(accJ + (odd_a ? M : 0));
+                const uint4 *srcO = (const uint4 *)(accJ + (odd_a ? 0 : M));
+                const uint4 *ownE = (const uint4 *)accJ, *ownO = (const uint4 *)(accJ + M);
+#pragma unroll
+                for (int qq = 0; qq < (G::QPW + 63) / 64; ++qq) {
+                    if (G::QPW % 64 != 0 && qq * 64 + lane >= G::QPW) break;
+                    const uint32_t q = qq * 64 + lane;
+                    uint32_t rE[4], rO[4];
+                    kara_rot4<M>(srcE, q, al, rE);
+                    kara_rot4<M>(srcO, q, al + odd_a, rO);
+                    const uint4 E4 = ownE[q], O4 = ownO[q];
+                    const uint32_t oE[4] = {E4.x, E4.y, E4.z, E4.w}, oO[4] = {O4.x, O4.y, O4.z, O4.w};
+                    uint32_t tE[4], tO[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t dE = rE[u] - oE[u], dO = rO[u] - oO[u];
+                        tE[u] = drop ? (dE + (1u << (drop - 1))) >> drop : dE;
+                        tO[u] = drop ? (dO + (1u << (drop - 1))) >> drop : dO;
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < ELL; ++jj) {
+#pragma unroll
+                        for (int h = 0; h < CH; ++h) {
+                            const uint32_t off = log2B * jj + 7 * h;
+                            const bool full = 7 * (h + 1) <= log2B;
+                            const uint32_t wdt = full ? 7u : (uint32_t)log2B - 7 * h;
+                            const uint32_t oe = full ? 64u : 0u, oo = full ? 63u : 0u;
+                            const uint32_t cE = (128u - oe) * 0x01010101u, nE = (128u + oe) * 0x01010101u;
+                            const uint32_t cO = (128u - oo) * 0x01010101u, nO = (128u + oo) * 0x01010101u;
+                            uint32_t pe = __builtin_amdgcn_ubfe(tE[3], off, wdt);
+                            pe |= __builtin_amdgcn_ubfe(tE[2], off, wdt) << 8;
+                            pe |= __builtin_amdgcn_ubfe(tE[1], off, wdt) << 16;
+                            pe |= __builtin_amdgcn_ubfe(tE[0], off, wdt) << 24;
+                            uint32_t po = __builtin_amdgcn_ubfe(tO[3], off, wdt);
+                            po |= __builtin_amdgcn_ubfe(tO[2], off, wdt) << 8;
+                            po |= __builtin_amdgcn_ubfe(tO[1], off, wdt) << 16;
+                            po |= __builtin_amdgcn_ubfe(tO[0], off, wdt) << 24;
+                            const int r = jc * G::RPC + jj * CH + h;
+                            uint32_t *sE = seq(r, 0), *sO = seq(r, 1);
+                            sE[M / 4 - q - 1] = (pe + cE) ^ 0x80808080u;
+                            sE[M / 2 - q - 1] = (nE - pe) ^ 0x80808080u;
+                            sO[M / 4 - q - 1] = (po + cO) ^ 0x80808080u;
+                            sO[M / 2 - q - 1] = (nO - po) ^ 0x80808080u;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();  // one wavefront: orders the digit writes before the fragment reads
+
+        // One product at a time: its MFMA accumulators (both components) are
+        // folded into the LDS accumulator before the next product starts, which
+        // keeps the kernel within the registers of two wavefronts per SIMD.
+        v4i C[2][G::NT];
+        // first A word of unit (row r, product p, key chunk c) for this lane
+        auto abase = [&](int r, int p, int c) { return seq(r, p) + (S0 + 64 * c * G::KC - G::DLOC) / 4; };
+        auto one_unit = [&](const int r, auto P_, const int c, v4i(&Bc)[2][G::KC], v4i(&Bn)[2][G::KC],
+                            const v4i *np) {
+            constexpr int p = decltype(P_)::value;
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int kb = 0; kb < G::KC; ++kb) Bn[j][kb] = np[j * JSTRIDE + kb * 64];
+            __builtin_amdgcn_sched_barrier(0);
+            const uint32_t *ab = abase(r, p, c);
+            auto afrag = [&](const int dd, v4i &A) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) A[k] = (int)ab[16 * dd + k];
+            };
+            v4i Af[2];
+            afrag(0, Af[0]);
+#pragma unroll
+            for (int dd = 0; dd < G::NDIAG; ++dd) {
+                const int dl = G::DLOC - 64 * dd;
+                if (dd + 1 < G::NDIAG) afrag(dd + 1, Af[(dd + 1) & 1]);
+#pragma unroll
+                for (int kb = 0; kb < G::KC; ++kb) {
+                    const int m0 = dl + 64 * kb;
+                    if (m0 >= 0 && m0 <= 64 * (G::NT - 1)) {
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            C[j][m0 / 64] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Af[dd & 1], Bc[j][kb], C[j][m0 / 64],
+                                                                                 0, 0, 0);
+                    }
+                }
+            }
+        };
+
+        const bool p1 = lane & 1, h1 = lane & 2;
+        auto rs = [&](const v4i &zc) -> uint32_t {  // limbs recombined mod 2^32, reduce-scatter over the quad
+            const uint32_t y0 = (uint32_t)zc[0] << (8 * limb), y1 = (uint32_t)zc[1] << (8 * limb);
+            const uint32_t y2 = (uint32_t)zc[2] << (8 * limb), y3 = (uint32_t)zc[3] << (8 * limb);
+            const uint32_t za = (p1 ? y1 : y0) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(p1 ? y0 : y1), 0xB1, 0xF, 0xF, false);
+            const uint32_t zb = (p1 ? y3 : y2) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(p1 ? y2 : y3), 0xB1, 0xF, 0xF, false);
+            return (h1 ? zb : za) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(h1 ? za : zb), 0x4E, 0xF, 0xF, false);
+        };
+        const int mb = 16 * g + 4 * limb + ss - 1;
+        constexpr int RS2 = (G::NCH % 2) ? 2 : 1;  // rows per unrolled group: an even number of units
+        constexpr int UG = RS2 * G::NCH;
+        static_assert(G::RV % RS2 == 0, "rows split into whole groups");
+
+        StaticFor<0, 3>::run([&](auto P_) {
+            constexpr int p = decltype(P_)::value;
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int t = 0; t < G::NT; ++t) C[j][t] = v4i{0, 0, 0, 0};
+#pragma unroll 1
+            for (int r = 0; r < G::RV; r += RS2) {
+                StaticFor<0, UG>::run([&](auto U_) {
+                    constexpr int u = decltype(U_)::value;
+                    constexpr int rr = u / G::NCH, c = u % G::NCH;
+                    const v4i *np;  // key fragments of the next unit
+                    if constexpr (u + 1 < UG) {
+                        constexpr int u2 = u + 1;
+                        np = frag(i, r + u2 / G::NCH, p, u2 % G::NCH);
+                    } else {
+                        const bool more = r + RS2 < G::RV;
+                        if constexpr (p < 2) np = more ? frag(i, r + RS2, p, 0) : frag(i, 0, p + 1, 0);
+                        else np = more ? frag(i, r + RS2, p, 0) : frag(inext < n ? inext : i, 0, 0, 0);
+                    }
+                    if constexpr (u % 2 == 0) one_unit(r + rr, IC<p>{}, c, B0, B1, np);
+                    else one_unit(r + rr, IC<p>{}, c, B1, B0, np);
+                });
+            }
+            if constexpr (p == 0) {
+                // V_e + V_o (bytewise, no carry between bytes) replaces V_e: every
+                // read of V_e was issued above, and one wavefront's LDS operations
+                // are performed in order
+#pragma unroll
+                for (int x = lane * 4; x < G::RV * G::SEQ_WORDS; x += 256) {
+                    const int rr = x / G::SEQ_WORDS, w = x % G::SEQ_WORDS;
+                    uint4 *pe4 = (uint4 *)(seq(rr, 0) + w);
+                    const uint4 e4 = *pe4, o4 = *(const uint4 *)(seq(rr, 1) + w);
+                    auto add8 = [](uint32_t a, uint32_t b) {
+                        return ((a & 0x7F7F7F7Fu) + (b & 0x7F7F7F7Fu)) ^ ((a ^ b) & 0x80808080u);
+                    };
+                    *pe4 = uint4{add8(e4.x, o4.x), add8(e4.y, o4.y), add8(e4.z, o4.z), add8(e4.w, o4.w)};
+                }
+            }
+            // fold product p: (ab)_e = P_e + Y P_o, (ab)_o = P_s - P_e - P_o; the
+            // offset correction of the step rides with P_e.  Coefficient -1 of the
+            // tiling is -(coefficient M - 1).  LDS atomic adds: lanes of one
+            // instruction touch distinct words, but later statements touch words
+            // of other lanes (m + 1), which plain read-modify-writes could reorder.
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                uint32_t *accE = accL + j * N, *accO = accE + M;
+#pragma unroll
+                for (int t = 0; t < G::NT; ++t) {
+                    const int m = 64 * t + mb;
+                    const bool wrap = t == 0 && mb < 0;
+                    const uint32_t x = rs(C[j][t]);
+                    if constexpr (p == 0) {
+                        const uint32_t *cp = corr + ((size_t)i * 2 + j) * N;
+                        const int mc = m & (M - 1);
+                        const uint32_t wE = cp[mc], wO = cp[M + mc];
+                        atomicAdd(&accE[wrap ? M - 1 : m], wrap ? wE - x : wE + x);
+                        atomicAdd(&accO[wrap ? M - 1 : m], wrap ? wO + x : wO - x);
+                    } else if constexpr (p == 1) {
+                        atomicAdd(&accE[m + 1], x);
+                        atomicAdd(&accO[wrap ? M - 1 : m], wrap ? x : 0u - x);
+                    } else {
+                        atomicAdd(&accO[wrap ? M - 1 : m], wrap ? 0u - x : x);
+                    }
+                }
+            }
+        });
+        __syncthreads();  // the accumulate completes before the next digits read it
+        i = inext;
+    }
+    __syncthreads();
+    for (int x = lane; x < 2 * N; x += 64) {
+        const int m = x & (N - 1);
+        row[x] = accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static int ilog2i(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
@@ -1281,8 +1530,9 @@ hipError_t launch_br_plain(const Geometry &G, uint32_t *acc, const uint32_t *ctN
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     static bool attr_set = false;
     if (!attr_set) {
-        hipFuncSetAttribute((const void *)k_br_plain, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
+        const hipError_t e = hipFuncSetAttribute((const void *)k_br_plain,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
         attr_set = true;
     }
     hipLaunchKernelGGL(k_br_plain, dim3(A), dim3(256), lds, s, acc, ctN, accs_per_ct, G.n, G.N,
@@ -1328,26 +1578,50 @@ static constexpr int br_kara_threads()
 {
     return BrKara<N, ELL, CH>::WPC == 1 ? 64 : 64 * BrKara<N, ELL, CH>::WAVES;
 }
-
-// Workgroups of the Karatsuba blind rotation resident on the whole device at once.
+// Rounds that fill every SIMD twice run k_br_kara1w2 (instantiated at N = 1024).
 template <int N, int ELL, int CH>
-static hipError_t br_kara_capacity(uint32_t *cap_out)
+static constexpr bool br_kara_two()
+{
+    return N == 1024;
+}
+
+// Resident capacity of the batched blind rotation on the current device.
+struct KaraFit {
+    uint32_t cap1 = 0;  // workgroups of br_kara_kernel resident at once
+    uint32_t cap2 = 0;  // of k_br_kara1w2 (0 when it is not used)
+    uint32_t round() const { return cap2 > cap1 ? cap2 : cap1; }
+};
+
+static hipError_t kernel_capacity(const void *k, int threads, size_t lds, int cus, uint32_t *cap)
+{
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int per_cu = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds);
+    if (e != hipSuccess) return e;
+    *cap = (uint32_t)std::max(1, per_cu) * (uint32_t)cus;
+    return hipSuccess;
+}
+
+template <int N, int ELL, int CH>
+static hipError_t br_kara_fit(KaraFit *out)
 {
     using GK = BrKara<N, ELL, CH>;
-    static uint32_t cap = 0;
-    if (!cap) {
-        hipError_t e = hipFuncSetAttribute(br_kara_kernel<N, ELL, CH>(), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)GK::LDS_BYTES);
-        int dev = 0, cus = 0, per_cu = 0;
-        if (e == hipSuccess) e = hipGetDevice(&dev);
+    static KaraFit fit;
+    if (!fit.cap1) {
+        KaraFit f;
+        int dev = 0, cus = 0;
+        hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, br_kara_kernel<N, ELL, CH>(),
-                                                             br_kara_threads<N, ELL, CH>(), GK::LDS_BYTES);
+            e = kernel_capacity(br_kara_kernel<N, ELL, CH>(), br_kara_threads<N, ELL, CH>(), GK::LDS_BYTES, cus,
+                                &f.cap1);
+        if constexpr (br_kara_two<N, ELL, CH>())
+            if (e == hipSuccess)
+                e = kernel_capacity((const void *)k_br_kara1w2<N, ELL, CH>, 64, GK::LDS2W_BYTES, cus, &f.cap2);
         if (e != hipSuccess) return e;
-        cap = (uint32_t)std::max(1, per_cu * cus);
+        fit = f;
     }
-    *cap_out = cap;
+    *out = fit;
     return hipSuccess;
 }
 
@@ -1362,17 +1636,27 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
     // each XCD's L2 once and shared, where a second round started by
     // completions would drift and re-fetch.  A round may begin inside a
     // sample's group of accumulators (a_base), so no round is left short.
-    uint32_t cap = 0;
-    hipError_t e0 = br_kara_capacity<N, ELL, CH>(&cap);
+    KaraFit fit;
+    hipError_t e0 = br_kara_fit<N, ELL, CH>(&fit);
     if (e0 != hipSuccess) return e0;
-    for (uint32_t a0 = 0; a0 < A; a0 += cap) {
-        const uint32_t cnt = std::min(cap, A - a0);
-        if constexpr (GK::WPC == 1)
-            hipLaunchKernelGGL((k_br_kara1w<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS_BYTES, s, acc, ctN, a0,
-                               accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
-        else
-            hipLaunchKernelGGL((k_br_kara<N, ELL, CH>), dim3(cnt), dim3(64 * GK::WAVES), GK::LDS_BYTES, s, acc,
-                               ctN, a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+    const uint32_t R = fit.round();
+    for (uint32_t a0 = 0; a0 < A; a0 += R) {
+        const uint32_t cnt = std::min(R, A - a0);
+        bool two = false;  // this round fills every SIMD twice
+        if constexpr (br_kara_two<N, ELL, CH>()) {
+            two = cnt > fit.cap1;
+            if (two)
+                hipLaunchKernelGGL((k_br_kara1w2<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS2W_BYTES, s, acc, ctN,
+                                   a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+        }
+        if (!two) {
+            if constexpr (GK::WPC == 1)
+                hipLaunchKernelGGL((k_br_kara1w<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS_BYTES, s, acc, ctN, a0,
+                                   accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+            else
+                hipLaunchKernelGGL((k_br_kara<N, ELL, CH>), dim3(cnt), dim3(64 * GK::WAVES), GK::LDS_BYTES, s, acc,
+                                   ctN, a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1404,15 +1688,16 @@ hipError_t br_kara_launches(const Geometry &G, uint32_t A, uint32_t accs_per_ct,
 {
     *launches = 0;
     if (!A) return hipSuccess;
+    (void)accs_per_ct;  // a round may split a sample's accumulators
     const int ch = digit_chunks(G.g_log2B);
-    uint32_t cap = 0;
     hipError_t e = hipErrorInvalidValue;
+    KaraFit fit;
 #define X(n_, l_, c_) \
-    if (G.N == n_ && G.g_ell == l_ && ch == c_) e = br_kara_capacity<n_, l_, c_>(&cap);
+    if (G.N == n_ && G.g_ell == l_ && ch == c_) e = br_kara_fit<n_, l_, c_>(&fit);
     FDFB_BR_MFMA_CASES(X)
 #undef X
     if (e != hipSuccess) return e;
-    *launches = (A + cap - 1) / cap;
+    *launches = (A + fit.round() - 1) / fit.round();
     return hipSuccess;
 }
 

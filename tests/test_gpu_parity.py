@@ -247,6 +247,36 @@ def test_blind_rotate_c2(c2, form):
         assert np.array_equal(got[a], refs[a]), a
 
 
+def test_blind_rotate_c2_full_and_short_rounds(c2):
+    """One rotation over a round that fills the device (on MI355X the
+    two-wavefronts-per-SIMD kernel) and a short second round (the
+    one-wavefront kernel), two accumulators per sample: every accumulator
+    equals the plain VALU form bit for bit, and those at the round boundary
+    and the ends match the oracle."""
+    ctx, ok = c2
+    p = W.C2
+    N = p.N
+    R = _resident_capacity(ctx)
+    per = 2
+    A = R + 6
+    assert ctx.br_launches(A, per) == 2
+    g = np.random.default_rng(41)
+    acc = u32(g, A, 2 * N)
+    ctN = g.integers(0, 2 * N, (A // per, p.n + 1)).astype(np.uint32)
+    say(f"blind_rotate C2 rounds A={A} R={R}")
+    d_acc, d_ref = fd.to_device(acc), fd.to_device(acc)
+    d_ct = fd.to_device(ctN)
+    ctx.blind_rotate(d_acc, d_ct, per, 0)
+    ctx.blind_rotate(d_ref, d_ct, per, fd.PLAIN)
+    torch.cuda.synchronize()
+    got = fd.to_host(d_acc)
+    assert np.array_equal(got, fd.to_host(d_ref))
+    picks = [0, R - 1, R, A - 1]
+    refs = run_oracle_many(lambda k: oracle.blind_rotate(p, ok.brk, ctN[picks[k] // per], acc[picks[k]]), len(picks))
+    for k, a in enumerate(picks):
+        assert np.array_equal(got[a], refs[k]), a
+
+
 def test_fdfb_c2_full_batch(c2):
     """The headline configuration at its full size: 1024 samples, one random
     LUT.  Sampled outputs are recomputed one by one by the oracle; every output
