@@ -87,6 +87,32 @@ def cpu_baseline(p, cts, lut, threads: int, sample: int):
                       f"({dt:.1f} s wall)"}
 
 
+def oracle_timing(threads: int):
+    """The oracle's time per bootstrap at the two plain-batch configurations,
+    on one thread and on `threads` threads (one sample per thread), on the
+    same kind of seeded inputs as the GPU runs."""
+    import oracle
+    import workloads as W
+    res = {}
+    for name, count1 in (("C1", 16), ("C2", 1)):
+        p = W.PRESETS[name]
+        keys = oracle.keygen(p, W.KEY_SEED[name])
+        lut = W.random_lut(W.LUT_SEED[name], p.t)
+        rot = [oracle.setup_polynomial(lut, p.N)]
+        msgs = W.messages(W.MSG_SEED[name], max(count1, threads), p.t)
+        cts = oracle.encrypt(p, keys.s, msgs, seed=W.MSG_SEED[name])
+        t0 = time.perf_counter()
+        oracle.fdfb_batch(keys, rot, np.zeros(count1, int), cts[:count1], threads=1)
+        one = (time.perf_counter() - t0) / count1
+        t0 = time.perf_counter()
+        oracle.fdfb_batch(keys, rot, np.zeros(threads, int), cts[:threads], threads=threads)
+        many = time.perf_counter() - t0
+        res[name] = {"s_per_bootstrap_1_thread": one, "bootstraps_per_s_1_thread": 1 / one,
+                     "threads": threads, "bootstraps_per_s_all_threads": threads / many,
+                     "sample": f"{count1} bootstraps on 1 thread, {threads} on {threads} threads"}
+    return res
+
+
 def serving_run(fd, torch, W, ctxs, presets, pools, lids, count, rate, max_batch=512, nstreams=3, seed=None):
     """Poisson request stream through the continuous-batching server.
     Returns throughput, request latency percentiles and batching counters."""
@@ -303,6 +329,8 @@ def main():
                     help="also time every parameter preset at batch 1024 this many steps (0 skips)")
     ap.add_argument("--mixed-steps", type=int, default=0,
                     help="also time the uneven two-degree batch (one multi-job submission) this many times")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="also time the oracle at C1 and C2 on one thread and on all host threads")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -399,6 +427,9 @@ def main():
     func = rate(func_units, phases["function_br"] / calls, ctx.br_launches(func_units, 1))
     both = rate(sign_units + func_units, (phases["sign_br"] + phases["function_br"]) / calls,
                 sign["launches_per_step"] + func["launches_per_step"])
+    # the dense int8 rate this device sustains on a register-only MFMA stream
+    mfma_tops, mfma_ms = fd.measure_mfma_peak()
+    print(f"[bench] measured int8 MFMA stream: {mfma_tops:.0f} TOPS", file=sys.stderr, flush=True)
     roofline = {"bound": "mfma", "kernel": sign_kernel, "achieved": sign["achieved"], "peak": PEAK_INT8_TOPS,
                 "unit": "TFLOP/s", "frac": sign["frac"], "traffic": load_traffic(sign_kernel),
                 "ops_per_launch_avg": sign["ops_per_launch_avg"], "avg_launch_ms": sign["avg_launch_ms"],
@@ -406,6 +437,10 @@ def main():
                 "function_rotation": dict(kernel=func_kernel, traffic=load_traffic(func_kernel), **func),
                 "all_rotations": {"achieved": both["achieved"], "frac": both["frac"],
                                   "executed_mfma_frac": both["executed_mfma_frac"]},
+                "measured_mfma_peak": {"tera_ops": mfma_tops, "ms": mfma_ms,
+                                       "what": "independent v_mfma_i32_16x16x64_i8 from registers on every "
+                                               "wave slot (fdfb_measure_mfma_peak)",
+                                       "executed_frac_of_measured": sign["achieved"] * 0.75 / mfma_tops},
                 "note": "int8 tera-ops/s of the schoolbook product work (63.4 G per accumulator); the "
                         "kernels issue 3/4 of it on MFMA (one Karatsuba level), executed_mfma_frac is that "
                         "rate over the peak; kernel is the sign rotations' kernel (2048 accumulators, the "
@@ -461,6 +496,12 @@ def main():
         print(f"[bench] cpu baseline: oracle on {threads} threads", file=sys.stderr, flush=True)
         cpu = cpu_baseline(p, cts, lut, threads, threads)
 
+    otime = None
+    if args.oracle_timing:
+        threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        print(f"[bench] oracle timing on 1 and {threads} threads", file=sys.stderr, flush=True)
+        otime = oracle_timing(threads)
+
     res = {
         "metric": METRIC,
         "value": B * K / wall,
@@ -492,6 +533,7 @@ def main():
         "mixed": mixed,
         "config_sweep": sweep,
         "cpu_baseline": cpu,
+        "oracle_timing": otime,
     }
     print(json.dumps(res), flush=True)
 

@@ -345,6 +345,15 @@ int fdfb_profile_read(fdfb_ctx *ctx, double *ms, uint32_t *calls);
 int fdfb_br_launches(fdfb_ctx *ctx, uint32_t accumulators, uint32_t per_ct, uint32_t flags,
                      uint32_t *launches);
 
+/* Calibration of the roofline: run a stream of independent int8 MFMAs
+ * (v_mfma_i32_16x16x64_i8, operands in registers, no memory traffic) on every
+ * resident workgroup slot of the current device, synchronously on the null
+ * stream, and store the sustained dense int8 rate in *tera_ops (10^12 ops/s,
+ * a multiply-add counting 2) and the timed launch's duration in *ms.  It
+ * allocates and frees a small output buffer.  FDFB_EINVAL on a null pointer,
+ * FDFB_EDEVICE on a HIP error. */
+int fdfb_measure_mfma_peak(double *tera_ops, double *ms);
+
 /* Raise or clear the abort flag; while raised, device entry points return
  * FDFB_EABORTED without enqueuing work. */
 void fdfb_set_abort(fdfb_ctx *ctx, int raised);

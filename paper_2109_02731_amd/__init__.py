@@ -61,7 +61,7 @@ EXPORTED = [
     "fdfb_keyswitch", "fdfb_modswitch", "fdfb_blind_rotate", "fdfb_sample_extract",
     "fdfb_packing_keyswitch", "fdfb_pubmux", "fdfb_encrypt_debug", "fdfb_decrypt_debug",
     "fdfb_export_keys", "fdfb_import_keys", "fdfb_get_key", "fdfb_profile", "fdfb_profile_read",
-    "fdfb_br_launches", "fdfb_set_abort", "fdfb_free", "fdfb_last_error",
+    "fdfb_br_launches", "fdfb_measure_mfma_peak", "fdfb_set_abort", "fdfb_free", "fdfb_last_error",
     "fdfb_server_create", "fdfb_server_submit", "fdfb_server_poll", "fdfb_server_wait",
     "fdfb_server_stats", "fdfb_server_destroy", "fdfb_affine",
 ]
@@ -101,6 +101,7 @@ def lib():
             "fdfb_profile_read": (i, [P, P, P]),
             "fdfb_set_abort": (None, [P, i]),
             "fdfb_br_launches": (i, [P, u32, u32, u32, P]),
+            "fdfb_measure_mfma_peak": (i, [P, P]),
             "fdfb_free": (None, [P]),
             "fdfb_last_error": (C.c_char_p, []),
             "fdfb_server_create": (i, [P, u32, u32, sz, u32, P]),
@@ -356,6 +357,14 @@ def to_device(a: np.ndarray, device="cuda"):
     """uint32 numpy array -> int32 torch tensor with the same bits."""
     import torch
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(device)
+
+
+def measure_mfma_peak() -> tuple[float, float]:
+    """Sustained dense int8 MFMA rate of the current device (tera-ops/s) and the
+    duration of the timed calibration launch (ms): fdfb_measure_mfma_peak."""
+    tops, ms = C.c_double(), C.c_double()
+    _check(lib().fdfb_measure_mfma_peak(C.byref(tops), C.byref(ms)))
+    return tops.value, ms.value
 
 
 def to_host(t) -> np.ndarray:

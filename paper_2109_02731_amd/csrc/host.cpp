@@ -968,6 +968,37 @@ int fdfb_br_launches(fdfb_ctx *c, uint32_t A, uint32_t per_ct, uint32_t flags, u
     return FDFB_OK;
 }
 
+int fdfb_measure_mfma_peak(double *tera_ops, double *ms)
+{
+    if (!tera_ops || !ms) return fail(FDFB_EINVAL, "null argument");
+    uint32_t blocks = 0;
+    K_TRY(fdfbk::mfma_stream_capacity(&blocks));
+    const uint32_t iters = 32768;  // about 40 ms at 3 POPS with every wave slot filled
+    int32_t *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto done = [&](int rc) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (out) (void)hipFree(out);
+        return rc;
+    };
+    hipError_t e = hipMalloc(&out, (size_t)blocks * 64 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = fdfbk::launch_mfma_stream(blocks, 256, out, nullptr);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+    if (e == hipSuccess) e = fdfbk::launch_mfma_stream(blocks, iters, out, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) return done(fail(FDFB_EDEVICE, std::string("mfma calibration: ") + hipGetErrorString(e)));
+    const double ops = (double)blocks * iters * 16 * (16.0 * 16 * 64 * 2);
+    *ms = t;
+    *tera_ops = t > 0 ? ops / (t * 1e-3) / 1e12 : 0.0;
+    return done(FDFB_OK);
+}
+
 void fdfb_set_abort(fdfb_ctx *c, int raised)
 {
     if (c) c->abort_flag.store(raised ? 1 : 0);

@@ -1447,6 +1447,49 @@ hipError_t launch_init_sign(const Geometry &G, const uint32_t *ctN, uint32_t B, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Calibration: a stream of independent int8 MFMAs from registers (no memory
+// traffic, operands with random-looking bytes), to measure the dense int8 rate
+// the device sustains on such data.  Sixteen accumulator chains per wavefront
+// keep the matrix pipe fed; the sums are stored so that nothing is optimised
+// away.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_mfma_stream(uint32_t iters, int32_t *__restrict__ out)
+{
+    // operand bytes spread like random digits and key limbs (a multiplicative hash of the lane)
+    const uint32_t h = (blockIdx.x * 64u + threadIdx.x + 1u) * 0x9E3779B1u;
+    const v4i a = {(int)h, (int)(h * 0x85EBCA77u), (int)(h * 0xC2B2AE3Du), (int)(h * 0x27D4EB2Fu)};
+    const v4i b = {(int)(h ^ 0x165667B1u), (int)(h * 0xD3A2646Cu), (int)(h * 0xFD7046C5u), (int)(h * 0xB55A4F09u)};
+    v4i c[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = v4i{k, 0, 0, 0};
+    for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) c[k] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c[k], 0, 0, 0);
+    }
+    int32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sum += c[k][0] + c[k][1] + c[k][2] + c[k][3];
+    out[(size_t)blockIdx.x * 64 + threadIdx.x] = sum;
+}
+
+hipError_t mfma_stream_capacity(uint32_t *blocks)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_mfma_stream, 64, 0);
+    if (e != hipSuccess) return e;
+    *blocks = (uint32_t)std::max(1, per_cu * cus);
+    return hipSuccess;
+}
+
+hipError_t launch_mfma_stream(uint32_t blocks, uint32_t iters, int32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mfma_stream, dim3(blocks), dim3(64), 0, s, iters, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_tfhe(const Geometry &G, const uint32_t *ctN, const int32_t *lut_ids, uint32_t B,
                             const int32_t *luts, int nluts, uint32_t *acc, hipStream_t s)
 {

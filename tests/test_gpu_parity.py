@@ -1,6 +1,7 @@
 """GPU parity: every stage of the HIP path against the CPU oracle, bit for bit,
 through the C ABI, for both kernel forms (batched MFMA and plain VALU)."""
 import dataclasses
+import os
 
 import numpy as np
 import pytest
@@ -293,13 +294,37 @@ def test_fdfb_c2_full_batch(c2):
     m, err = ctx.decrypt_debug(out)
     assert np.array_equal(m, lut[msgs])
     r0, r1 = oracle.setup_polynomial(lut, p.N)
-    sample = [0, 1, 511, 777, 1022, 1023]
+    # 64 samples: both ends, the middle, and a seeded spread over the batch
+    sample = sorted({0, 1, 511, 512, 1022, 1023} |
+                    set(np.random.default_rng(64).choice(B, 58, replace=False).tolist()))
+    say(f"oracle on {len(sample)} samples")
     refs = run_oracle_many(lambda k: oracle.fdfb(ok, r0, r1, cts[sample[k]]), len(sample))
     for k, idx in enumerate(sample):
         assert np.array_equal(out[idx], refs[k]), idx
     say("fdfb C2 plain B=1024")
     outp = _bootstrap(ctx, cts, [lid] * B, fd.PLAIN, p.n + 1)
     assert np.array_equal(outp, out)
+
+
+@pytest.mark.skipif(os.environ.get("FDFB_FULL_PARITY") != "1",
+                    reason="all 1024 samples through the oracle take several minutes of host time; "
+                           "set FDFB_FULL_PARITY=1 to run")
+def test_fdfb_c2_all_1024_vs_oracle(c2):
+    """Every output of the headline batch against the oracle, bit for bit."""
+    ctx, ok = c2
+    p = W.C2
+    B = 1024
+    lut = W.random_lut(W.LUT_SEED["C2"], p.t)
+    lid = ctx.register_lut(lut)
+    msgs = W.messages(W.MSG_SEED["C2"], B, p.t)
+    cts = ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C2"])
+    out = _bootstrap(ctx, cts, [lid] * B, 0, p.n + 1)
+    rot = [oracle.setup_polynomial(lut, p.N)]
+    for lo in range(0, B, 128):
+        ref = oracle.fdfb_batch(ok, rot, np.zeros(128, int), cts[lo:lo + 128], threads=16)
+        bad = np.nonzero((ref != out[lo:lo + 128]).any(axis=1))[0]
+        say(f"oracle samples {lo}..{lo + 127}: {len(bad)} mismatches")
+        assert len(bad) == 0, (lo + bad[:8]).tolist()
 
 
 # ----------------------------------------------------------------------------
@@ -399,6 +424,14 @@ def test_fdfb_n2048_vs_oracle(keys_2048):
     refs = run_oracle_many(lambda k: oracle.fdfb(ok, r0, r1, cts[k]), len(msgs))
     for k in range(len(msgs)):
         assert np.array_equal(out[k], refs[k]), k
+
+
+def test_measure_mfma_peak():
+    """The calibration stream runs and reports a rate no higher than the
+    device's published dense int8 peak (5.0 POPS) allows."""
+    tops, ms = fd.measure_mfma_peak()
+    say(f"int8 MFMA stream: {tops:.0f} TOPS in {ms:.1f} ms")
+    assert ms > 0 and 0 < tops <= 1.05 * 5000
 
 
 def test_br_launch_count(c2):
