@@ -1,16 +1,25 @@
 // HIP kernels of the FDFB path for gfx950 (MI355X).
 //
 // Arithmetic is exact: every ring coefficient is a uint32_t and wraps mod
-// 2^32 (q = Q = 2^32).  The blind rotation has two forms that give identical
-// bits:
-//  * k_br_mfma  -- batched: one accumulator per workgroup of 2 or 4 waves;
-//    each external product is a Toeplitz contraction on int8 MFMA (16x16x64)
-//    with 8-bit key limbs and int32 accumulation, recombined mod 2^32;
+// 2^32 (q = Q = 2^32).  The blind rotation has three forms that give
+// identical bits:
+//  * Karatsuba (default): k_br_kara1w (N <= 1024, one wavefront per
+//    accumulator), k_br_kara1w2 (N = 1024, rounds that put two wavefronts on
+//    every SIMD) and k_br_kara (N = 2048, two wavefronts per output
+//    component).  Each external product splits the ring into even and odd
+//    halves and computes three half-size Toeplitz contractions on int8 MFMA
+//    (16x16x64) with 8-bit key limbs and int32 accumulation, recombined mod
+//    2^32;
+//  * k_br_mfma -- the direct form: one full-size contraction per digit row;
 //  * k_br_plain -- one accumulator per workgroup, uint32 multiply-add on the
 //    vector ALUs (the comparison form).
+// Key switching (k_keyswitch_mfma), the public mux (k_pubmux) and the
+// element-wise steps complete the bootstrap.
 #include <hip/hip_runtime.h>
-#include <algorithm>
 #include <stdint.h>
+
+#include <algorithm>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -1426,6 +1435,39 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // ---------------------------------------------------------------------------
 static int ilog2i(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
 
+// One-time set-up per device (function attributes and occupancy belong to a
+// device): make(dev, &value) runs once per device, under a lock; devices past
+// the table are set up on every call.
+template <typename T>
+struct PerDevice {
+    static constexpr int kDevices = 64;
+    std::mutex mu;
+    bool have[kDevices] = {};
+    T val[kDevices] = {};
+    template <typename F>
+    hipError_t get(T *out, F make)
+    {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        std::lock_guard<std::mutex> lock(mu);
+        const bool tab = dev >= 0 && dev < kDevices;
+        if (tab && have[dev]) {
+            *out = val[dev];
+            return hipSuccess;
+        }
+        T v{};
+        e = make(dev, &v);
+        if (e != hipSuccess) return e;
+        if (tab) {
+            val[dev] = v;
+            have[dev] = true;
+        }
+        *out = v;
+        return hipSuccess;
+    }
+};
+
 hipError_t launch_modswitch(const Geometry &G, const uint32_t *cts, uint32_t B, uint32_t *ctN,
                             hipStream_t s)
 {
@@ -1571,13 +1613,13 @@ hipError_t launch_br_plain(const Geometry &G, uint32_t *acc, const uint32_t *ctN
     const int R = 2 * G.g_ell;
     const size_t lds = 4 * (size_t)2 * G.N + 4 * (size_t)R * 2 * G.N + 2 * (size_t)R * 2 * G.N;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    static bool attr_set = false;
-    if (!attr_set) {
-        const hipError_t e = hipFuncSetAttribute((const void *)k_br_plain,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static PerDevice<bool> attr;
+    bool ok = false;
+    hipError_t e0 = attr.get(&ok, [](int, bool *v) {
+        *v = true;
+        return hipFuncSetAttribute((const void *)k_br_plain, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    if (e0 != hipSuccess) return e0;
     hipLaunchKernelGGL(k_br_plain, dim3(A), dim3(256), lds, s, acc, ctN, accs_per_ct, G.n, G.N,
                        G.g_log2B, G.g_ell, brk_raw);
     return hipGetLastError();
@@ -1588,13 +1630,14 @@ static hipError_t launch_br_mfma_t(const Geometry &G, uint32_t *acc, const uint3
                                    uint32_t accs_per_ct, const void *brk_frag, hipStream_t s)
 {
     using GM = BrMfma<N, ELL, CH>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_br_mfma<N, ELL, CH>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)GM::LDS_BYTES);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static PerDevice<bool> attr;
+    bool ok = false;
+    hipError_t e0 = attr.get(&ok, [](int, bool *v) {
+        *v = true;
+        return hipFuncSetAttribute((const void *)k_br_mfma<N, ELL, CH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)GM::LDS_BYTES);
+    });
+    if (e0 != hipSuccess) return e0;
     hipLaunchKernelGGL((k_br_mfma<N, ELL, CH>), dim3(A), dim3(64 * GM::WAVES), GM::LDS_BYTES, s, acc, ctN,
                        accs_per_ct, G.n, (const v4i *)brk_frag, G.g_log2B);
     return hipGetLastError();
@@ -1649,23 +1692,18 @@ template <int N, int ELL, int CH>
 static hipError_t br_kara_fit(KaraFit *out)
 {
     using GK = BrKara<N, ELL, CH>;
-    static KaraFit fit;
-    if (!fit.cap1) {
-        KaraFit f;
-        int dev = 0, cus = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    static PerDevice<KaraFit> fits;
+    return fits.get(out, [](int dev, KaraFit *f) {
+        int cus = 0;
+        hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
             e = kernel_capacity(br_kara_kernel<N, ELL, CH>(), br_kara_threads<N, ELL, CH>(), GK::LDS_BYTES, cus,
-                                &f.cap1);
+                                &f->cap1);
         if constexpr (br_kara_two<N, ELL, CH>())
             if (e == hipSuccess)
-                e = kernel_capacity((const void *)k_br_kara1w2<N, ELL, CH>, 64, GK::LDS2W_BYTES, cus, &f.cap2);
-        if (e != hipSuccess) return e;
-        fit = f;
-    }
-    *out = fit;
-    return hipSuccess;
+                e = kernel_capacity((const void *)k_br_kara1w2<N, ELL, CH>, 64, GK::LDS2W_BYTES, cus, &f->cap2);
+        return e;
+    });
 }
 
 template <int N, int ELL, int CH>
