@@ -278,6 +278,36 @@ def test_blind_rotate_c2_full_and_short_rounds(c2):
         assert np.array_equal(got[a], refs[k]), a
 
 
+@pytest.mark.parametrize("A,zeros", [(2048, 0.5), (1500, 0.05)])
+def test_blind_rotate_c2_skips_and_partial_round(c2, A, zeros):
+    """Rounds of the two-wavefronts-per-SIMD kernel (more accumulators than
+    SIMDs) with skipped steps: a share of the a_i are 0, and the last 3 of
+    every row, so the key prefetch of the final live step stops short of the
+    end.  A = 1500 leaves some SIMDs with one wavefront.  Every accumulator
+    equals the plain form; a few match the oracle."""
+    ctx, ok = c2
+    p = W.C2
+    N = p.N
+    per = 2
+    g = np.random.default_rng(43)
+    acc = u32(g, A, 2 * N)
+    ctN = g.integers(0, 2 * N, (A // per, p.n + 1)).astype(np.uint32)
+    ctN[:, 1:][g.random((A // per, p.n)) < zeros] = 0
+    ctN[:, -3:] = 0
+    say(f"blind_rotate C2 skips A={A} zeros={zeros}")
+    d_acc, d_ref = fd.to_device(acc), fd.to_device(acc)
+    d_ct = fd.to_device(ctN)
+    ctx.blind_rotate(d_acc, d_ct, per, 0)
+    ctx.blind_rotate(d_ref, d_ct, per, fd.PLAIN)
+    torch.cuda.synchronize()
+    got = fd.to_host(d_acc)
+    assert np.array_equal(got, fd.to_host(d_ref))
+    picks = [0, A // 2 + 1, A - 1]
+    refs = run_oracle_many(lambda k: oracle.blind_rotate(p, ok.brk, ctN[picks[k] // per], acc[picks[k]]), len(picks))
+    for k, a in enumerate(picks):
+        assert np.array_equal(got[a], refs[k]), a
+
+
 def test_fdfb_c2_full_batch(c2):
     """The headline configuration at its full size: 1024 samples, one random
     LUT.  Sampled outputs are recomputed one by one by the oracle; every output
