@@ -307,6 +307,33 @@ def config_sweep(fd, torch, W, B: int, steps: int):
     return {"batch": B, "steps": steps, "presets": res}
 
 
+def batch_sweep(fd, torch, W, ctx, steps: int, sizes=(128, 256, 512, 1024, 2048, 4096)):
+    """The bench configuration (n=630 N=1024, one table) at several batch
+    sizes: bootstraps/s, time per batch and blind-rotation launches, to show
+    what batching buys and what a batch costs in latency."""
+    p = W.C2
+    lut = W.random_lut(W.LUT_SEED["C2"], p.t)
+    lid = ctx.register_lut(lut)
+    res = []
+    for B in sizes:
+        msgs = W.messages(W.MSG_SEED["C2"] + B, B, p.t)
+        cts = fd.to_device(ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C2"] + B))
+        ids = torch.full((B,), lid, dtype=torch.int32, device="cuda")
+        out = torch.empty((B, p.n + 1), dtype=torch.int32, device="cuda")
+        ctx.bootstrap_batch(cts, ids, out)
+        torch.cuda.synchronize()
+        ok = bool(np.array_equal(ctx.decrypt_debug(fd.to_host(out))[0], lut[msgs]))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.bootstrap_batch(cts, ids, out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res.append({"batch": B, "bootstraps_per_s": B / dt, "ms_per_batch": dt * 1e3, "correct": ok,
+                    "br_launches": ctx.br_launches(B * p.boot_ell, p.boot_ell) + ctx.br_launches(B, 1)})
+        print(f"[bench] batch {B}: {B / dt:.0f} bootstraps/s, {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"steps": steps, "sizes": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,6 +356,8 @@ def main():
                     help="also time every parameter preset at batch 1024 this many steps (0 skips)")
     ap.add_argument("--mixed-steps", type=int, default=0,
                     help="also time the uneven two-degree batch (one multi-job submission) this many times")
+    ap.add_argument("--batch-sweep", type=int, default=0, metavar="STEPS",
+                    help="also time the bench configuration at batch 128..4096 this many steps (0 skips)")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="also time the oracle at C1 and C2 on one thread and on all host threads")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -496,6 +525,11 @@ def main():
         print(f"[bench] cpu baseline: oracle on {threads} threads", file=sys.stderr, flush=True)
         cpu = cpu_baseline(p, cts, lut, threads, threads)
 
+    bsweep = None
+    if args.batch_sweep > 0:
+        print("[bench] batch-size sweep", file=sys.stderr, flush=True)
+        bsweep = batch_sweep(fd, torch, W, ctx, args.batch_sweep)
+
     otime = None
     if args.oracle_timing:
         threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
@@ -533,6 +567,7 @@ def main():
         "mixed": mixed,
         "config_sweep": sweep,
         "cpu_baseline": cpu,
+        "batch_sweep": bsweep,
         "oracle_timing": otime,
     }
     print(json.dumps(res), flush=True)

@@ -1193,9 +1193,14 @@ __global__ __launch_bounds__(64, 1) void k_br_kara1w(uint32_t *__restrict__ acc_
 // k_br_kara1w instead: its register use allows one wavefront per SIMD, so the
 // dispatcher cannot stack two on one SIMD while another idles.  Same digits,
 // products and results as k_br_kara1w.
+// WV = 2 gives each accumulator two wavefronts, each with the digit rows of
+// one input component (its digits, its products, its folds; the step's
+// correction is added by the first), with one key buffer that is refilled
+// block by block; two barriers per step.  It halves the time of a step for
+// rounds small enough to give every wavefront a SIMD of its own.
 // ---------------------------------------------------------------------------
-template <int N, int ELL, int CH>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_br_kara1w2(uint32_t *__restrict__ acc_g,
+template <int N, int ELL, int CH, int WV>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) void k_br_kara1w2(uint32_t *__restrict__ acc_g,
                                                     const uint32_t *__restrict__ ctN, uint32_t a_base,
                                                     uint32_t accs_per_ct, int n,
                                                     const v4i *__restrict__ bfrag,
@@ -1209,10 +1214,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     uint32_t *digL = accL + 2 * N;      // [RV][V_e (then V_e + V_o), V_o][SEQ_WORDS]
     auto seq = [&](int r, int p) { return digL + (r * 2 + (p & 1)) * G::SEQ_WORDS; };
 
+    static_assert(WV == 1 || WV == 2, "one wavefront, or one per component's digit rows");
+    constexpr int RW = G::RV / WV;  // digit rows per wavefront: those of component hw when WV = 2
     const int lane = threadIdx.x & 63;
+    const int hw = WV == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int r0 = hw * RW;  // first digit row of this wavefront
     const uint32_t a_idx = a_base + blockIdx.x;  // accumulator; sample a_idx / accs_per_ct
     uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
-    for (int x = lane; x < 2 * N; x += 64) {
+    for (int x = threadIdx.x; x < 2 * N; x += 64 * WV) {
         const int m = x & (N - 1);
         accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)] = row[x];
     }
@@ -1235,7 +1244,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     int i = next_live(-1);
     v4i B0[2][G::KC], B1[2][G::KC];
     {
-        const v4i *bp = frag(i < n ? i : 0, 0, 0, 0);
+        const v4i *bp = frag(i < n ? i : 0, r0, 0, 0);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -1250,7 +1259,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         {
             const uint32_t al = a >> 1, odd_a = a & 1;
 #pragma unroll
-            for (int jc = 0; jc < 2; ++jc) {
+            for (int jc0 = 0; jc0 < 2 / WV; ++jc0) {
+                const int jc = WV == 1 ? jc0 : hw;
                 const uint32_t *accJ = accL + jc * N;
                 const uint4 *srcE = (const uint4 *)(accJ + (odd_a ? M : 0));
                 const uint4 *srcO = (const uint4 *)(accJ + (odd_a ? 0 : M));
@@ -1300,7 +1310,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 }
             }
         }
-        __syncthreads();  // one wavefront: orders the digit writes before the fragment reads
+        __syncthreads();  // digits written, and every read of the accumulator done before a fold
 
         // One product at a time: its MFMA accumulators (both components) are
         // folded into the LDS accumulator before the next product starts, which
@@ -1359,31 +1369,75 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int t = 0; t < G::NT; ++t) C[j][t] = v4i{0, 0, 0, 0};
+            if constexpr (WV == 1) {
 #pragma unroll 1
-            for (int r = 0; r < G::RV; r += RS2) {
-                StaticFor<0, UG>::run([&](auto U_) {
-                    constexpr int u = decltype(U_)::value;
-                    constexpr int rr = u / G::NCH, c = u % G::NCH;
-                    const v4i *np;  // key fragments of the next unit
-                    if constexpr (u + 1 < UG) {
-                        constexpr int u2 = u + 1;
-                        np = frag(i, r + u2 / G::NCH, p, u2 % G::NCH);
-                    } else {
-                        const bool more = r + RS2 < G::RV;
-                        if constexpr (p < 2) np = more ? frag(i, r + RS2, p, 0) : frag(i, 0, p + 1, 0);
-                        else np = more ? frag(i, r + RS2, p, 0) : frag(inext < n ? inext : i, 0, 0, 0);
-                    }
-                    if constexpr (u % 2 == 0) one_unit(r + rr, IC<p>{}, c, B0, B1, np);
-                    else one_unit(r + rr, IC<p>{}, c, B1, B0, np);
-                });
+                for (int r = 0; r < G::RV; r += RS2) {
+                    StaticFor<0, UG>::run([&](auto U_) {
+                        constexpr int u = decltype(U_)::value;
+                        constexpr int rr = u / G::NCH, c = u % G::NCH;
+                        const v4i *np;  // key fragments of the next unit
+                        if constexpr (u + 1 < UG) {
+                            constexpr int u2 = u + 1;
+                            np = frag(i, r + u2 / G::NCH, p, u2 % G::NCH);
+                        } else {
+                            const bool more = r + RS2 < G::RV;
+                            if constexpr (p < 2) np = more ? frag(i, r + RS2, p, 0) : frag(i, 0, p + 1, 0);
+                            else np = more ? frag(i, r + RS2, p, 0) : frag(inext < n ? inext : i, 0, 0, 0);
+                        }
+                        if constexpr (u % 2 == 0) one_unit(r + rr, IC<p>{}, c, B0, B1, np);
+                        else one_unit(r + rr, IC<p>{}, c, B1, B0, np);
+                    });
+                }
+            } else {
+                // this wavefront's rows, with one key buffer: each key block is
+                // reloaded for the next unit once its last diagonal is done
+#pragma unroll 1
+                for (int rr = 0; rr < RW; ++rr) {
+                    StaticFor<0, G::NCH>::run([&](auto C_) {
+                        constexpr int c = decltype(C_)::value;
+                        const v4i *np;
+                        if constexpr (c + 1 < G::NCH) np = frag(i, r0 + rr, p, c + 1);
+                        else if (rr + 1 < RW) np = frag(i, r0 + rr + 1, p, 0);
+                        else if constexpr (p < 2) np = frag(i, r0, p + 1, 0);
+                        else np = frag(inext < n ? inext : i, r0, 0, 0);
+                        const uint32_t *ab = abase(r0 + rr, p, c);
+                        auto afrag = [&](const int dd, v4i &A) {
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) A[k] = (int)ab[16 * dd + k];
+                        };
+                        v4i Af[2];
+                        afrag(0, Af[0]);
+#pragma unroll
+                        for (int dd = 0; dd < G::NDIAG; ++dd) {
+                            const int dl = G::DLOC - 64 * dd;
+                            if (dd + 1 < G::NDIAG) afrag(dd + 1, Af[(dd + 1) & 1]);
+#pragma unroll
+                            for (int kb = 0; kb < G::KC; ++kb) {
+                                const int m0 = dl + 64 * kb;
+                                if (m0 >= 0 && m0 <= 64 * (G::NT - 1)) {
+#pragma unroll
+                                    for (int j = 0; j < 2; ++j)
+                                        C[j][m0 / 64] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Af[dd & 1], B0[j][kb],
+                                                                                             C[j][m0 / 64], 0, 0, 0);
+                                }
+                            }
+                            // key block kb is last used by diagonal kb + NT - 1
+                            if (dd >= G::NT - 1) {
+                                const int kd = dd - (G::NT - 1);
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) B0[j][kd] = np[j * JSTRIDE + kd * 64];
+                            }
+                        }
+                    });
+                }
             }
             if constexpr (p == 0) {
                 // V_e + V_o (bytewise, no carry between bytes) replaces V_e: every
                 // read of V_e was issued above, and one wavefront's LDS operations
                 // are performed in order
 #pragma unroll
-                for (int x = lane * 4; x < G::RV * G::SEQ_WORDS; x += 256) {
-                    const int rr = x / G::SEQ_WORDS, w = x % G::SEQ_WORDS;
+                for (int x = lane * 4; x < RW * G::SEQ_WORDS; x += 256) {
+                    const int rr = r0 + x / G::SEQ_WORDS, w = x % G::SEQ_WORDS;
                     uint4 *pe4 = (uint4 *)(seq(rr, 0) + w);
                     const uint4 e4 = *pe4, o4 = *(const uint4 *)(seq(rr, 1) + w);
                     auto add8 = [](uint32_t a, uint32_t b) {
@@ -1408,7 +1462,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     if constexpr (p == 0) {
                         const uint32_t *cp = corr + ((size_t)i * 2 + j) * N;
                         const int mc = m & (M - 1);
-                        const uint32_t wE = cp[mc], wO = cp[M + mc];
+                        // the correction of the whole step, added once
+                        const uint32_t wE = hw == 0 ? cp[mc] : 0u, wO = hw == 0 ? cp[M + mc] : 0u;
                         atomicAdd(&accE[wrap ? M - 1 : m], wrap ? wE - x : wE + x);
                         atomicAdd(&accO[wrap ? M - 1 : m], wrap ? wO + x : wO - x);
                     } else if constexpr (p == 1) {
@@ -1424,7 +1479,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         i = inext;
     }
     __syncthreads();
-    for (int x = lane; x < 2 * N; x += 64) {
+    for (int x = threadIdx.x; x < 2 * N; x += 64 * WV) {
         const int m = x & (N - 1);
         row[x] = accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)];
     }
@@ -1664,7 +1719,9 @@ static constexpr int br_kara_threads()
 {
     return BrKara<N, ELL, CH>::WPC == 1 ? 64 : 64 * BrKara<N, ELL, CH>::WAVES;
 }
-// Rounds that fill every SIMD twice run k_br_kara1w2 (instantiated at N = 1024).
+// k_br_kara1w2 is instantiated at N = 1024: rounds with more accumulators
+// than SIMDs run it with one wavefront per accumulator, rounds of at most one
+// accumulator per two SIMDs with two wavefronts per accumulator.
 template <int N, int ELL, int CH>
 static constexpr bool br_kara_two()
 {
@@ -1674,7 +1731,7 @@ static constexpr bool br_kara_two()
 // Resident capacity of the batched blind rotation on the current device.
 struct KaraFit {
     uint32_t cap1 = 0;  // workgroups of br_kara_kernel resident at once
-    uint32_t cap2 = 0;  // of k_br_kara1w2 (0 when it is not used)
+    uint32_t cap2 = 0;  // of k_br_kara1w2<.., 1> (0 when it is not used)
     uint32_t round() const { return cap2 > cap1 ? cap2 : cap1; }
 };
 
@@ -1699,9 +1756,13 @@ static hipError_t br_kara_fit(KaraFit *out)
         if (e == hipSuccess)
             e = kernel_capacity(br_kara_kernel<N, ELL, CH>(), br_kara_threads<N, ELL, CH>(), GK::LDS_BYTES, cus,
                                 &f->cap1);
-        if constexpr (br_kara_two<N, ELL, CH>())
+        if constexpr (br_kara_two<N, ELL, CH>()) {
             if (e == hipSuccess)
-                e = kernel_capacity((const void *)k_br_kara1w2<N, ELL, CH>, 64, GK::LDS2W_BYTES, cus, &f->cap2);
+                e = kernel_capacity((const void *)k_br_kara1w2<N, ELL, CH, 1>, 64, GK::LDS2W_BYTES, cus, &f->cap2);
+            if (e == hipSuccess)  // attribute only: rounds of WV = 2 are sized from cap1
+                e = hipFuncSetAttribute((const void *)k_br_kara1w2<N, ELL, CH, 2>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)GK::LDS2W_BYTES);
+        }
         return e;
     });
 }
@@ -1723,14 +1784,21 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
     const uint32_t R = fit.round();
     for (uint32_t a0 = 0; a0 < A; a0 += R) {
         const uint32_t cnt = std::min(R, A - a0);
-        bool two = false;  // this round fills every SIMD twice
+        bool done = false;
         if constexpr (br_kara_two<N, ELL, CH>()) {
-            two = cnt > fit.cap1;
-            if (two)
-                hipLaunchKernelGGL((k_br_kara1w2<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS2W_BYTES, s, acc, ctN,
-                                   a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+            if (cnt > fit.cap1) {
+                // more accumulators than one wavefront per SIMD holds: two per SIMD
+                hipLaunchKernelGGL((k_br_kara1w2<N, ELL, CH, 1>), dim3(cnt), dim3(64), GK::LDS2W_BYTES, s, acc,
+                                   ctN, a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+                done = true;
+            } else if (2 * cnt <= fit.cap1) {
+                // a small round: two wavefronts per accumulator still give each one a SIMD
+                hipLaunchKernelGGL((k_br_kara1w2<N, ELL, CH, 2>), dim3(cnt), dim3(128), GK::LDS2W_BYTES, s, acc,
+                                   ctN, a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
+                done = true;
+            }
         }
-        if (!two) {
+        if (!done) {
             if constexpr (GK::WPC == 1)
                 hipLaunchKernelGGL((k_br_kara1w<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS_BYTES, s, acc, ctN, a0,
                                    accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);

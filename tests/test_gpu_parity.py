@@ -278,12 +278,13 @@ def test_blind_rotate_c2_full_and_short_rounds(c2):
         assert np.array_equal(got[a], refs[k]), a
 
 
-@pytest.mark.parametrize("A,zeros", [(2048, 0.5), (1500, 0.05)])
+@pytest.mark.parametrize("A,zeros", [(2048, 0.5), (1500, 0.05), (512, 0.3), (96, 0.0)])
 def test_blind_rotate_c2_skips_and_partial_round(c2, A, zeros):
-    """Rounds of the two-wavefronts-per-SIMD kernel (more accumulators than
-    SIMDs) with skipped steps: a share of the a_i are 0, and the last 3 of
-    every row, so the key prefetch of the final live step stops short of the
-    end.  A = 1500 leaves some SIMDs with one wavefront.  Every accumulator
+    """Rounds of the N = 1024 kernel forms with skipped steps: a share of the
+    a_i are 0, and the last 3 of every row, so the key prefetch of the final
+    live step stops short of the end.  2048 and 1500 accumulators run one
+    wavefront per accumulator, two per SIMD (1500 leaves some SIMDs with
+    one); 512 and 96 run two wavefronts per accumulator.  Every accumulator
     equals the plain form; a few match the oracle."""
     ctx, ok = c2
     p = W.C2
