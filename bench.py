@@ -450,8 +450,13 @@ def main():
                 "executed_mfma_frac": achieved * 0.75 / PEAK_INT8_TOPS}  # one Karatsuba level: 3 of 4 products
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    sign_kernel = "k_br_kara1w2<1024, 3, 1>" if sign_units > 4 * cus else "k_br_kara1w<1024, 3, 1>"
-    func_kernel = "k_br_kara1w2<1024, 3, 1>" if func_units > 4 * cus else "k_br_kara1w<1024, 3, 1>"
+
+    def kernel_for(units):  # the library's choice for one round of this many accumulators
+        if units > 4 * cus:
+            return "k_br_kara1w2<1024, 3, 1, 1>"
+        return "k_br_kara1w2<1024, 3, 1, 2>" if 2 * units <= 4 * cus else "k_br_kara1w<1024, 3, 1>"
+
+    sign_kernel, func_kernel = kernel_for(sign_units), kernel_for(func_units)
     sign = rate(sign_units, phases["sign_br"] / calls, ctx.br_launches(sign_units, p.boot_ell))
     func = rate(func_units, phases["function_br"] / calls, ctx.br_launches(func_units, 1))
     both = rate(sign_units + func_units, (phases["sign_br"] + phases["function_br"]) / calls,
