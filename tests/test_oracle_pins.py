@@ -430,3 +430,41 @@ def test_sampler_statistics():
     z = np.array([oracle.gauss(3, 4, i, 1000.0) for i in range(4000)], dtype=np.float64)
     assert abs(z.mean()) < 60 and abs(z.std() / 1000.0 - 1) < 0.05
     assert oracle.gauss(3, 4, 0, 0.0) == 0
+
+
+# ----------------------------------------------------------------------------
+# forced faults are caught by decryption (host only)
+# ----------------------------------------------------------------------------
+def test_forced_faults_are_detected(oracle_keys_c1):
+    """Faults planted on the host show up as decryption mismatches against
+    the plaintext function: input noise pushed past half a slot moves m to
+    m + 1, and one corrupted blind-rotation key row garbles the rotation.
+    Untouched inputs in the same batch still decrypt to f(m)."""
+    k = oracle_keys_c1
+    p = W.C1
+    t, delta = p.t, M32 // p.t
+    lut = W.random_lut(W.LUT_SEED["C1"] + 9, t)
+    while len(set(lut.tolist())) < t // 2:  # a table that tells neighbouring slots apart
+        lut = (lut * 3 + 1) % t
+    msgs = np.tile(np.arange(t, dtype=np.uint32), 2)
+    cts = oracle.encrypt(p, k.s, msgs, seed=W.MSG_SEED["C1"] + 9)
+    rot = [oracle.setup_polynomial(lut, p.N)]
+    ids = np.zeros(len(msgs), int)
+
+    # (a) inflated noise on the first copy: +3/4 of a slot on the body
+    noisy = cts.copy()
+    noisy[:t, 0] = (noisy[:t, 0].astype(np.uint64) + (3 * delta) // 4).astype(np.uint32)  # body b
+    m, _ = oracle.decrypt(oracle.fdfb_batch(k, rot, ids, noisy), k.s, p.log2_t)
+    want = lut[msgs]
+    assert np.array_equal(m[t:], want[t:])
+    shifted = lut[(msgs[:t] + 1) % t]
+    assert np.array_equal(m[:t], shifted)
+    assert (m[:t] != want[:t]).sum() == (shifted != want[:t]).sum() > 0
+
+    # (b) one corrupted row of the blind-rotation key
+    g = np.random.default_rng(9)
+    bad = dataclasses.replace(k, brk=k.brk.copy())
+    bad.brk[3, 0, 1] ^= g.integers(0, M32, p.N, dtype=np.uint64).astype(np.uint32)
+    m, err = oracle.decrypt(oracle.fdfb_batch(bad, rot, ids, cts), k.s, p.log2_t)
+    assert (m != want).sum() >= len(msgs) // 4
+    assert np.max(np.abs(err)) >= delta // 4
