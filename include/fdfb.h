@@ -328,7 +328,11 @@ void fdfb_server_destroy(fdfb_server *srv);
 #define FDFB_NPHASES 7
 
 /* Enable (1) or disable (0) timing: while enabled, every fdfb_bootstrap_batch
- * call records a hipEvent at each phase boundary on its stream. */
+ * call records a hipEvent at each phase boundary on its stream.  A context
+ * created while the environment variable FDFB_TRACE is set (to anything but
+ * "0") starts with timing enabled, and fdfb_free prints the milliseconds per
+ * call of each phase, over the calls not yet read, to stderr (a diagnostic:
+ * the events of every call are kept until then). */
 int fdfb_profile(fdfb_ctx *ctx, int enable);
 
 /* Wait for the recorded events, add the elapsed milliseconds of each phase

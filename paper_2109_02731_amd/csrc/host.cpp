@@ -7,10 +7,10 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
-#include <cstdlib>
 #include <vector>
 
 #include "fdfb.h"
@@ -597,6 +597,14 @@ using namespace fdfbi;
 // ============================================================================
 // C ABI
 // ============================================================================
+// FDFB_TRACE set (and not "0") when a context is created: record the phase
+// events of every bootstrap call on it and print their summary on fdfb_free.
+static void apply_trace_env(fdfb_ctx &c)
+{
+    const char *v = std::getenv("FDFB_TRACE");
+    if (v && *v && std::strcmp(v, "0") != 0) c.profiling = c.trace = true;
+}
+
 extern "C" {
 
 const char *fdfb_last_error(void) { return g_last_error.c_str(); }
@@ -609,6 +617,7 @@ int fdfb_keygen_from_seed(const fdfb_params *params, uint64_t seed, fdfb_ctx **o
     if (rc) return rc;
     fdfb_ctx *c = new (std::nothrow) fdfb_ctx();
     if (!c) return fail(FDFB_ENOMEM, "context allocation failed");
+    apply_trace_env(*c);
     c->P = *params;
     c->seed = seed;
     c->geom = geometry_of(*params);
@@ -890,6 +899,7 @@ int fdfb_import_keys(const void *buf, size_t len, fdfb_ctx **out)
     if (len < need) return fail(FDFB_EINVAL, "truncated key blob");
     fdfb_ctx *c = new (std::nothrow) fdfb_ctx();
     if (!c) return fail(FDFB_ENOMEM, "context allocation failed");
+    apply_trace_env(*c);
     c->P = P;
     c->seed = seed;
     c->geom = geometry_of(P);
@@ -1004,6 +1014,20 @@ void fdfb_set_abort(fdfb_ctx *c, int raised)
     if (c) c->abort_flag.store(raised ? 1 : 0);
 }
 
-void fdfb_free(fdfb_ctx *c) { delete c; }
+void fdfb_free(fdfb_ctx *c)
+{
+    if (c && c->trace) {
+        static const char *const names[FDFB_NPHASES] = {"modswitch_init", "sign_br",     "extract_bits", "packing_ks",
+                                                        "pubmux",         "function_br", "output"};
+        double ms[FDFB_NPHASES];
+        uint32_t calls = 0;
+        if (fdfb_profile_read(c, ms, &calls) == FDFB_OK && calls) {
+            std::fprintf(stderr, "fdfb trace: %u bootstrap calls, ms per call:", calls);
+            for (int k = 0; k < FDFB_NPHASES; ++k) std::fprintf(stderr, " %s %.3f", names[k], ms[k] / calls);
+            std::fprintf(stderr, "\n");
+        }
+    }
+    delete c;
+}
 
 }  // extern "C"

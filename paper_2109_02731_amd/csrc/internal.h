@@ -51,6 +51,7 @@ struct fdfb_ctx {
     std::atomic<int> abort_flag{0};
 
     bool profiling = false;
+    bool trace = false;  // FDFB_TRACE: print the phase timings when the context is freed
     std::vector<hipEvent_t> prof_events;  // FDFB_NPHASES + 1 per recorded call
 
     ~fdfb_ctx()

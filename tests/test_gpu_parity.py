@@ -457,6 +457,21 @@ def test_fdfb_n2048_vs_oracle(keys_2048):
         assert np.array_equal(out[k], refs[k]), k
 
 
+def test_trace_env_prints_phase_times(capfd, monkeypatch):
+    """FDFB_TRACE at context creation: the phase timings of its bootstrap
+    calls are printed to stderr when the context is freed."""
+    monkeypatch.setenv("FDFB_TRACE", "1")
+    p = W.C1
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C1"])
+    lid = ctx.register_lut(W.random_lut(W.LUT_SEED["C1"], p.t))
+    cts = ctx.encrypt_debug(W.messages(W.MSG_SEED["C1"], 8, p.t), seed=W.MSG_SEED["C1"])
+    for _ in range(2):
+        _bootstrap(ctx, cts, [lid] * 8, 0, p.n + 1)
+    ctx.free()
+    err = capfd.readouterr().err
+    assert "fdfb trace: 2 bootstrap calls" in err and "function_br" in err, err[-500:]
+
+
 def test_measure_mfma_peak():
     """The calibration stream runs and reports a rate no higher than the
     device's published dense int8 peak (5.0 POPS) allows."""
