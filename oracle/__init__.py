@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
     sampler's floating-point steps are fixed)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
                                "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

@@ -20,7 +20,12 @@
  *
  * Parity status: every function below is pinned by a CPU test against an
  * independent fact (brute force, closed form, exact identity or the
- * noise-free limit) except where a header says "parity unpinned".
+ * noise-free limit) except where a header says "parity unpinned".  The noise
+ * is pinned separately, stage by stage: every key's noise deviation, and the
+ * variance each stage of the bootstrap adds, against the error analysis of
+ * Sec. 2 and Theorem "Correctness of the Bootstrapping", two-sided, with a
+ * different deviation for each key; the failure probability of Sec. 4 is
+ * pinned to Table II.
  */
 #include <math.h>
 #include <stdint.h>

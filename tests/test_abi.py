@@ -30,11 +30,16 @@ def test_library_exports_every_declared_symbol():
     assert sorted(fd.EXPORTED) == names
 
 
-@pytest.mark.parametrize("preset", ["C1", "C2"])
+@pytest.mark.parametrize("preset", ["C1", "C2", "C1S"])
 def test_keys_equal_oracle_keys(preset, request):
-    p = W.PRESETS[preset]
+    """Same seed, independent implementations: every key word agrees.  C1S
+    draws every key with its own deviation, so a deviation taken for the wrong
+    key in either implementation shows up here (the oracle's are pinned by the
+    noise checks)."""
+    p = W.C1S if preset == "C1S" else W.PRESETS[preset]
     seed = W.KEY_SEED[preset]
-    ok = request.getfixturevalue("oracle_keys_c1" if preset == "C1" else "oracle_keys_c2")
+    ok = oracle.keygen(p, seed) if preset == "C1S" else \
+        request.getfixturevalue("oracle_keys_c1" if preset == "C1" else "oracle_keys_c2")
     ctx = fd.Context.keygen(p, seed)
     for which, ref in enumerate([ok.s, ok.sf, ok.brk, ok.pk, ok.ksk]):
         got = ctx.get_key(which)
@@ -46,6 +51,16 @@ def test_exact_keys_equal_oracle(oracle_keys_c1_exact):
     ctx = fd.Context.keygen(p, W.KEY_SEED["C1"])
     for which, ref in enumerate([oracle_keys_c1_exact.brk, oracle_keys_c1_exact.pk, oracle_keys_c1_exact.ksk]):
         assert np.array_equal(ctx.get_key(which + 2), ref.reshape(-1))
+
+
+def test_encrypt_debug_uses_the_fresh_deviation():
+    """Fresh samples of the library at C1S equal the oracle's (whose noise
+    deviation is pinned to sigma_lwe)."""
+    p = W.C1S
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C1S"])
+    ok = oracle.keygen(p, W.KEY_SEED["C1S"])
+    msgs = W.messages(6, 64, p.t)
+    assert np.array_equal(ctx.encrypt_debug(msgs, seed=9), oracle.encrypt(p, ok.s, msgs, seed=9))
 
 
 def test_encrypt_decrypt_debug_match_oracle(oracle_keys_c1):

@@ -17,6 +17,9 @@ Parameter sets (q = Q = 2^32 throughout):
   at q = 2^32 (no security claim).
 * ``C4`` -- parameters for the NN-shaped circuit: n=750, N=2048, t=32,
   gadget base 2^7 ell=4, boot base 2 (ell_boot=5).
+* ``C1S`` -- C1's shape with four distinct noise deviations (fresh samples,
+  blind-rotation key, packing key, key switching key) and one public-mux
+  digit, for the per-stage noise checks.
 
 The packing key (LWE -> RLWE) uses base 2^4 with the key-switch ell, and the
 sign decomposition inside the public mux uses base 4 with
@@ -86,12 +89,19 @@ C4 = Params(n=750, N=2048, log2_t=5, g_log2B=7, g_ell=4, ks_log2B=4, ks_ell=5,
             sigma_lwe=_Q * 2.0 ** -24, sigma_glwe=0.25,
             sigma_pk=0.25, sigma_ks=_Q * 2.0 ** -24)
 
+# C1's shape with a different deviation for every key and for fresh samples
+# (each a factor of 4 or more from the others), so that the noise of every
+# stage can be told apart; one public-mux digit of base 8 (t = 8).
+C1S = Params(n=64, N=256, log2_t=3, g_log2B=8, g_ell=2, ks_log2B=4, ks_ell=4,
+             pk_log2B=4, pk_ell=4, boot_log2B=3, boot_ell=1,
+             sigma_lwe=2.0 ** 16, sigma_glwe=64.0, sigma_pk=1024.0, sigma_ks=4096.0)
+
 PRESETS = {"C1": C1, "C2": C2, "C3B": C3B, "C4": C4}
 
 # Seeds fixed per configuration: key, message, LUT.
-KEY_SEED = {"C1": 1001, "C2": 1002, "C3B": 1003, "C4": 1004}
-MSG_SEED = {"C1": 2001, "C2": 2002, "C3B": 2003, "C4": 2004}
-LUT_SEED = {"C1": 3001, "C2": 3002, "C3B": 3003, "C4": 3004}
+KEY_SEED = {"C1": 1001, "C2": 1002, "C3B": 1003, "C4": 1004, "C1S": 1005}
+MSG_SEED = {"C1": 2001, "C2": 2002, "C3B": 2003, "C4": 2004, "C1S": 2005}
+LUT_SEED = {"C1": 3001, "C2": 3002, "C3B": 3003, "C4": 3004, "C1S": 3005}
 ARRIVAL_SEED = 4000
 
 
