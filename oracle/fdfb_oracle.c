@@ -261,27 +261,42 @@ void or_blind_rotate(const or_params *P, const uint32_t *brk, const uint32_t *ct
 }
 
 /* ------------------------------------------------------------------------ */
-/* Rotation polynomials, Sec. 3.3, Fig. 2 "SetupPolynomial".                 */
-/* Reading R4: the table holds f(m) unscaled (Theorem "rotation polynomial"  */
-/* states coefficient = f(m)); the scale Delta is applied once, in PubMux.   */
-/* Reading R5: the windows of neighbouring m overlap; the loop order          */
-/* (m ascending, e ascending) is kept and later writes win.                  */
+/* Rotation polynomials, Sec. 3.3 (Theorem "rotation polynomial"; Fig. 2    */
+/* builds them window by window).  The property they must have: for every   */
+/* y in the window of m -- the y whose cyclic distance mod 2N from           */
+/* round(2N/t) m is at most ceil(N/t) -- coefficient 0 of rotP_0 X^y         */
+/* (y < N) or of rotP_1 X^y (y >= N) equals f(m).  Each y in [0, 2N) is     */
+/* taken in turn: its owner m is found and the one coefficient that         */
+/* coefficient 0 of the product reads is set; y in no window leaves it 0.   */
+/* Reading R4: the table holds f(m) unscaled (the theorem states            */
+/* coefficient = f(m)); the scale Delta is applied once, in PubMux.         */
+/* Reading R5: neighbouring windows overlap at their ends; there the        */
+/* larger m owns y (the construction's later write).                        */
 /* ------------------------------------------------------------------------ */
 void or_setup_polynomial(const uint32_t *lut, uint32_t t, uint32_t N, int32_t *p0, int32_t *p1)
 {
     memset(p0, 0, sizeof(int32_t) * N);
     memset(p1, 0, sizeof(int32_t) * N);
-    int32_t w = (int32_t)((N + t - 1) / t);       /* ceil(N/t)               */
-    int64_t step = (int64_t)((2 * N + t / 2) / t); /* round(2N/t)            */
-    for (uint32_t m = 0; m < t; ++m) {
-        for (int32_t e = -w; e <= w; ++e) {
-            int64_t y = (step * (int64_t)m + e) % (int64_t)(2 * N);
-            if (y < 0) y += 2 * N;
-            int32_t v = (int32_t)lut[m];
+    const int64_t w = (int64_t)((N + t - 1) / t);       /* ceil(N/t)    */
+    const int64_t step = (int64_t)((2 * N + t / 2) / t); /* round(2N/t)  */
+    const int64_t twoN = 2 * (int64_t)N;
+    for (int64_t y = 0; y < twoN; ++y) {
+        int64_t owner = -1;
+        for (int64_t m = (int64_t)t - 1; m >= 0 && owner < 0; --m) {
+            const int64_t d = ((y - step * m) % twoN + twoN) % twoN;
+            if (d <= w || d >= twoN - w) owner = m;      /* cyclic distance <= w */
+        }
+        if (owner < 0) continue;
+        const int32_t v = (int32_t)lut[owner];
+        /* coefficient 0 of X^y p: p_0 for y = 0, -p_{N-y} for 0 < y < N     */
+        /* (X^N = -1); for y >= N, X^y p = -X^(y-N) p                         */
+        if (y < (int64_t)N) {
             if (y == 0) p0[0] = v;
-            else if (y < (int64_t)N) p0[N - y] = -v;
-            else if (y == (int64_t)N) p1[0] = -v;
-            else p1[2 * N - y] = v;                /* N - y' with y' = y - N */
+            else p0[N - y] = -v;
+        } else {
+            const int64_t z = y - N;
+            if (z == 0) p1[0] = -v;
+            else p1[N - z] = v;
         }
     }
 }
