@@ -74,7 +74,23 @@ def load_traffic(kernel: str):
     return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    """Host CPU model name and logical core count (nproc)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(p, cts, lut, threads: int, sample: int):
+    """The oracle on the host: `sample` bootstraps of the bench batch, one per
+    thread on `threads` threads, and one bootstrap alone on one thread."""
     import oracle
     import workloads as W
     keys = oracle.keygen(p, W.KEY_SEED["C2"])
@@ -82,9 +98,14 @@ def cpu_baseline(p, cts, lut, threads: int, sample: int):
     t0 = time.perf_counter()
     oracle.fdfb_batch(keys, rot, np.zeros(sample, int), cts[:sample], threads=threads)
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.fdfb_batch(keys, rot, np.zeros(1, int), cts[sample:sample + 1], threads=1)
+    one = time.perf_counter() - t1
+    model, nproc = host_cpu()
     return {"value": sample / dt, "unit": "bootstraps/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sample} of the 1024 samples, one oracle bootstrap per thread "
-                      f"({dt:.1f} s wall)"}
+            "sample": f"samples 0..{sample - 1} of the 1024-sample batch, one oracle bootstrap per thread on "
+                      f"{threads} threads ({dt:.1f} s wall), and sample {sample} alone on one thread",
+            "s_per_bootstrap_1_thread": one, "host_nproc": nproc, "host_cpu_model": model}
 
 
 def oracle_timing(threads: int):
@@ -186,39 +207,100 @@ def serving_bench(fd, torch, W, ctx2, count):
 
 
 def mixed_bench(fd, torch, W, ctx2, steps: int):
-    """Uneven batch over two ring degrees (2048 samples at n=630 N=1024 and
-    2048 at n=750 N=2048, 64 tables per half, Zipf(1.2) ids): one
-    fdfb_bootstrap_multi submission vs the two jobs one after the other."""
+    """Config 3, the uneven batch over two ring degrees: 2048 samples at n=630
+    N=1024 and 2048 at n=750 N=2048, 64 tables per half, Zipf(1.2) ids.  One
+    multi-job submission whose blind rotations run in one persistent
+    work-queue launch per phase, the same captured in a HIP graph (one graph
+    launch per submission), and the jobs rotated in their own launches."""
     halves = [("C2", W.C2, ctx2), ("C3B", W.C3B, None)]
-    jobs = []
+    jobs, meta = [], []
     for name, p, c in halves:
         c = c or fd.Context.keygen(p, W.KEY_SEED[name])
-        lids = np.array([c.register_lut(W.random_lut(W.LUT_SEED[name] * 100 + j, p.t)) for j in range(64)],
-                        dtype=np.int32)
+        tables = [W.random_lut(W.LUT_SEED[name] * 100 + j, p.t) for j in range(64)]
+        lids = np.array([c.register_lut(tb) for tb in tables], dtype=np.int32)
         which = W.zipf_indices(W.LUT_SEED[name], 2048, 64, 1.2)
-        cts = fd.to_device(c.encrypt_debug(W.messages(W.MSG_SEED[name], 2048, p.t), seed=W.MSG_SEED[name]))
+        msgs = W.messages(W.MSG_SEED[name], 2048, p.t)
+        cts = fd.to_device(c.encrypt_debug(msgs, seed=W.MSG_SEED[name]))
         ids = torch.from_numpy(lids[which]).cuda()
         out = torch.empty((2048, p.n + 1), dtype=torch.int32, device="cuda")
         jobs.append((c, cts, ids, out, 0))
+        meta.append((c, np.array([tables[w][x] for w, x in zip(which, msgs)])))
 
-    def run(multi: bool) -> float:
+    def timed(fn) -> float:
+        fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            if multi:
-                fd.bootstrap_multi(jobs)
-            else:
-                for c, cts, ids, out, fl in jobs:
-                    c.bootstrap_batch(cts, ids, out, fl)
+            fn()
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    run(True)
-    t_multi, t_seq = run(True), run(False)
+    t_queue = timed(lambda: fd.bootstrap_multi(jobs, use_queue=True))
+    ok = all(np.array_equal(c.decrypt_debug(fd.to_host(j[3]))[0], want) for j, (c, want) in zip(jobs, meta))
+    t_jobs = timed(lambda: fd.bootstrap_multi(jobs, use_queue=False))
+    g = fd.MultiGraph(jobs, use_queue=True)
+    t_graph = timed(lambda: g.replay())
+    ok = ok and all(np.array_equal(c.decrypt_debug(fd.to_host(j[3]))[0], want) for j, (c, want) in zip(jobs, meta))
+    g.close()
     return {"workload": "2048 samples n=630 N=1024 t=16 + 2048 samples n=750 N=2048 t=32, "
                         "64 tables per half, Zipf(1.2) ids",
-            "bootstraps_per_s": 4096 / t_multi, "ms_per_submission": t_multi * 1e3,
-            "ms_jobs_in_sequence": t_seq * 1e3, "steps": steps}
+            "bootstraps_per_s": 4096 / t_graph, "ms_per_submission": t_graph * 1e3,
+            "what": "one HIP graph launch per submission; blind rotations in one persistent work-queue launch "
+                    "per phase for both ring degrees",
+            "ms_queue_submission": t_queue * 1e3, "ms_jobs_in_own_launches": t_jobs * 1e3,
+            "correct": bool(ok), "steps": steps}
+
+
+def nn_bench(fd, torch, W, steps: int):
+    """Config 4, the NN-shaped circuit: x in Z_32^784 -> dense 784->128 on LWE
+    samples -> FDFB ReLU on the 128 outputs (extracted) -> dense 128->10 ->
+    key switch (n=750, N=2048, gadget 2^7 x 4, L_boot = 2), time per
+    inference with every output checked against the plaintext evaluation."""
+    p = W.C4
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C4"])
+    relu = W.named_luts(p.t)["relu"]
+    lid = ctx.register_lut(relu)
+    x, w1, w2 = W.nn_inputs(W.MSG_SEED["C4"], p.t)
+    cts = fd.to_device(ctx.encrypt_debug(x, seed=W.MSG_SEED["C4"]))
+    d_w1, d_w2 = torch.from_numpy(w1).cuda(), torch.from_numpy(w2).cuda()
+    ids = torch.full((128,), lid, dtype=torch.int32, device="cuda")
+    h = torch.empty((128, p.n + 1), dtype=torch.int32, device="cuda")
+    hq = torch.empty((128, p.N + 1), dtype=torch.int32, device="cuda")
+    y = torch.empty((10, p.N + 1), dtype=torch.int32, device="cuda")
+    yo = torch.empty((10, p.n + 1), dtype=torch.int32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def infer(mark=False):
+        if mark:
+            ev[0].record()
+        fd.affine(d_w1, cts, h)
+        if mark:
+            ev[1].record()
+        ctx.bootstrap_batch(h, ids, hq, flags=fd.OUT_EXTRACTED)
+        if mark:
+            ev[2].record()
+        fd.affine(d_w2, hq, y)
+        ctx.keyswitch(y, yo)
+        if mark:
+            ev[3].record()
+
+    infer()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infer()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    infer(mark=True)
+    torch.cuda.synchronize()
+    hp = (w1.astype(np.int64) @ x.astype(np.int64)) % p.t
+    yp = (w2.astype(np.int64) @ relu[hp].astype(np.int64)) % p.t
+    ok = bool(np.array_equal(ctx.decrypt_debug(fd.to_host(yo))[0], yp))
+    return {"workload": "784 -> 128 -> 10 on LWE samples, FDFB ReLU on 128 outputs, n=750 N=2048 t=32",
+            "ms_per_inference": dt * 1e3, "inferences_per_s": 1 / dt, "bootstraps_per_inference": 128,
+            "phase_ms": {"affine_784_128": ev[0].elapsed_time(ev[1]), "bootstraps_128": ev[1].elapsed_time(ev[2]),
+                         "affine_128_10_and_keyswitch": ev[2].elapsed_time(ev[3])},
+            "correct": ok, "steps": steps}
 
 
 def multi_lut_bench(fd, torch, W, ctx, p, d_cts, B: int, L: int, steps: int, single_ms: float):
@@ -342,7 +424,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--serving-requests", type=int, default=300,
+    ap.add_argument("--serving-requests", type=int, default=4000,
                     help="requests per serving run (0 skips the serving measurement)")
     ap.add_argument("--multi-lut", type=int, default=4, metavar="L",
                     help="also time L tables per sample on the bench batch (0 skips)")
@@ -354,8 +436,12 @@ def main():
                     help="also time the one-rotation TFHE-style bootstrap this many steps (0 skips)")
     ap.add_argument("--config-sweep", type=int, default=0, metavar="STEPS",
                     help="also time every parameter preset at batch 1024 this many steps (0 skips)")
-    ap.add_argument("--mixed-steps", type=int, default=0,
-                    help="also time the uneven two-degree batch (one multi-job submission) this many times")
+    ap.add_argument("--mixed-steps", type=int, default=2,
+                    help="also time the uneven two-degree batch (one multi-job submission) this many times (0 skips)")
+    ap.add_argument("--nn-steps", type=int, default=3,
+                    help="also time the 784->128->10 circuit this many inferences (0 skips)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (the fixed plan rule issues the blind rotations)")
     ap.add_argument("--batch-sweep", type=int, default=0, metavar="STEPS",
                     help="also time the bench configuration at batch 128..4096 this many steps (0 skips)")
     ap.add_argument("--oracle-timing", action="store_true",
@@ -396,6 +482,14 @@ def main():
     def step(flags=0):
         ctx.bootstrap_batch(d_cts, d_ids, d_out, flags=flags)
 
+    tuned = None
+    if not args.no_tune:
+        # the autotuner times every issue plan of the two rotation phases of
+        # this batch (2048 sign and 1024 function accumulators) and records the
+        # fastest; the timed steps use them
+        print("[bench] autotune", file=sys.stderr, flush=True)
+        tuned = {"sign_rotations": ctx.autotune(B * p.boot_ell, p.boot_ell),
+                 "function_rotation": ctx.autotune(B, 1)}
     print(f"[bench] keys ready; warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -451,7 +545,16 @@ def main():
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
 
-    def kernel_for(units):  # the library's choice for one round of this many accumulators
+    def kernel_for(units):  # the kernel the library issues for one round of this many accumulators
+        form = ctx.get_plan(units)["form"]
+        if form == "queue":
+            return "k_br_queue<1024, 3, 1, 2048, 2, 2>"
+        if form == "1w":
+            return "k_br_kara1w<1024, 3, 1>"
+        if form == "1w2":
+            return "k_br_kara1w2<1024, 3, 1, 1>"
+        if form == "2w":
+            return "k_br_kara1w2<1024, 3, 1, 2>"
         if units > 4 * cus:
             return "k_br_kara1w2<1024, 3, 1, 1>"
         return "k_br_kara1w2<1024, 3, 1, 2>" if 2 * units <= 4 * cus else "k_br_kara1w<1024, 3, 1>"
@@ -464,22 +567,33 @@ def main():
     # the dense int8 rate this device sustains on a register-only MFMA stream
     mfma_tops, mfma_ms = fd.measure_mfma_peak()
     print(f"[bench] measured int8 MFMA stream: {mfma_tops:.0f} TOPS", file=sys.stderr, flush=True)
+    def hbm(traffic, ms_per_launch):
+        if not traffic:
+            return None
+        gbs = traffic / (ms_per_launch * 1e-3) / 1e9
+        return {"achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS}
+
+    sign_traffic, func_traffic = load_traffic(sign_kernel), load_traffic(func_kernel)
     roofline = {"bound": "mfma", "kernel": sign_kernel, "achieved": sign["achieved"], "peak": PEAK_INT8_TOPS,
-                "unit": "TFLOP/s", "frac": sign["frac"], "traffic": load_traffic(sign_kernel),
+                "unit": "TOPS", "frac": sign["frac"], "traffic": sign_traffic,
+                "hbm": hbm(sign_traffic, sign["avg_launch_ms"]),
                 "ops_per_launch_avg": sign["ops_per_launch_avg"], "avg_launch_ms": sign["avg_launch_ms"],
                 "launches_per_step": sign["launches_per_step"], "executed_mfma_frac": sign["executed_mfma_frac"],
-                "function_rotation": dict(kernel=func_kernel, traffic=load_traffic(func_kernel), **func),
+                "function_rotation": dict(kernel=func_kernel, traffic=func_traffic,
+                                          hbm=hbm(func_traffic, func["avg_launch_ms"]), **func),
                 "all_rotations": {"achieved": both["achieved"], "frac": both["frac"],
                                   "executed_mfma_frac": both["executed_mfma_frac"]},
                 "measured_mfma_peak": {"tera_ops": mfma_tops, "ms": mfma_ms,
                                        "what": "independent v_mfma_i32_16x16x64_i8 from registers on every "
                                                "wave slot (fdfb_measure_mfma_peak)",
                                        "executed_frac_of_measured": sign["achieved"] * 0.75 / mfma_tops},
-                "note": "int8 tera-ops/s of the schoolbook product work (63.4 G per accumulator); the "
-                        "kernels issue 3/4 of it on MFMA (one Karatsuba level), executed_mfma_frac is that "
-                        "rate over the peak; kernel is the sign rotations' kernel (2048 accumulators, the "
-                        "larger share of the step), function_rotation the one of the 1024 function "
-                        "accumulators, all_rotations both together"}
+                "note": "unit TOPS: 10^12 int8 multiply-add halves per second.  achieved counts the schoolbook "
+                        "product work of the method (63.4 G int8 ops per accumulator and rotation); the "
+                        "kernels issue 3/4 of it on MFMA (one exact Karatsuba level), executed_mfma_frac is "
+                        "the issued rate over the peak; kernel is the sign rotations' kernel (2048 "
+                        "accumulators, the larger share of the step), function_rotation the one of the 1024 "
+                        "function accumulators, all_rotations both together; hbm is the counted HBM traffic "
+                        "per launch over the launch time"}
 
     multi_lut = None
     if args.multi_lut > 0:
@@ -514,6 +628,11 @@ def main():
     if args.config_sweep > 0:
         sweep = config_sweep(fd, torch, W, B, args.config_sweep)
 
+    nn = None
+    if args.nn_steps > 0:
+        print("[bench] NN-shaped circuit", file=sys.stderr, flush=True)
+        nn = nn_bench(fd, torch, W, args.nn_steps)
+
     mixed = None
     if args.mixed_steps > 0:
         print("[bench] uneven two-degree batch", file=sys.stderr, flush=True)
@@ -526,8 +645,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        # the host's CPU share on a one-GPU machine is 16 threads (os.cpu_count()
+        # reports the whole machine there)
         threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
-        print(f"[bench] cpu baseline: oracle on {threads} threads", file=sys.stderr, flush=True)
+        print(f"[bench] cpu baseline: oracle on {threads} threads and on one", file=sys.stderr, flush=True)
         cpu = cpu_baseline(p, cts, lut, threads, threads)
 
     bsweep = None
@@ -570,6 +691,8 @@ def main():
         "tfhe_yardstick": tfhe,
         "direct_form": direct,
         "mixed": mixed,
+        "nn_circuit": nn,
+        "tuned": tuned,
         "config_sweep": sweep,
         "cpu_baseline": cpu,
         "batch_sweep": bsweep,

@@ -18,9 +18,16 @@
  *    hipStream_t passed as void* (NULL = the null stream).  Device work is
  *    enqueued asynchronously on `stream`; the call returns once it is queued.
  *  - A context (fdfb_ctx) owns the evaluation keys in device memory and the
- *    secret keys in host memory (for the *_debug calls).  Calls on one
- *    context must not overlap from several threads; distinct contexts are
- *    independent.
+ *    secret keys in host memory (for the *_debug calls).  Every call on a
+ *    context takes the context's lock, so any thread may call at any time;
+ *    calls that enqueue device work are ordered on their own streams only.
+ *    Distinct contexts are independent.
+ *  - Device scratch of direct calls comes from a pool per (context, stream):
+ *    calls on one stream reuse its block in stream order, calls on different
+ *    streams never share one.  A block that must grow is replaced, and the
+ *    replaced block stays allocated until fdfb_release_scratch or fdfb_free,
+ *    so work already enqueued or captured in a HIP graph never reads freed
+ *    memory.
  *  - Results are bit-identical for identical inputs whatever the batch size,
  *    batch composition, kernel form (Karatsuba, direct or plain) or stream.
  */
@@ -116,16 +123,26 @@ int fdfb_register_lut(fdfb_ctx *ctx, const uint32_t *table, int32_t *lut_id);
  *              s_F) when FDFB_OUT_EXTRACTED is set
  *   flags      FDFB_OUT_EXTRACTED | FDFB_PLAIN | FDFB_DIRECT (FDFB_ENOTSUP when the plain form
  *              cannot hold the parameter set, e.g. N = 2048 with ell = 4)
- * Scratch memory is taken from a pool owned by the context and grown on
- * demand (hipMalloc) the first time a larger B is seen.  B = 0 is a no-op.
- * After one call with at least this B (keys uploaded, scratch sized), the
- * call enqueues kernels only and can be captured into a HIP graph.
- * Errors: FDFB_EINVAL (null pointer with B > 0), FDFB_ENOMEM, FDFB_EDEVICE.
- * lut_ids are validated on the device: an out-of-range id yields all-zero
- * output for that sample.
+ * Scratch comes from the context's block for `stream`, replaced by a larger
+ * one (hipMalloc) the first time a larger B is seen on that stream.  B = 0 is
+ * a no-op.  After one call with at least this B on the same stream (keys
+ * uploaded, scratch sized), the call enqueues kernels only and can be
+ * captured into a HIP graph; a graph replays into the scratch block of the
+ * stream it was captured on, so replays must not overlap other calls on
+ * that stream.
+ * Errors: FDFB_EINVAL (null pointer with B > 0), FDFB_ENOMEM, FDFB_EDEVICE,
+ * FDFB_EABORTED.  lut_ids are read on the device: an id that is not a
+ * registered table gives that sample an all-zero accumulator (its output is
+ * not a bootstrap of anything) and sets FDFB_DEVERR_LUT_ID in the context's
+ * device error bits (fdfb_device_errors).
  */
 int fdfb_bootstrap_batch(fdfb_ctx *ctx, const uint32_t *d_cts, const int32_t *d_lut_ids,
                          uint32_t B, uint32_t *d_out, uint32_t flags, void *stream);
+
+/* Upload everything a call with these flags needs (keys, registered tables,
+ * the direct key layout for FDFB_DIRECT) without enqueuing work, so that
+ * later calls only enqueue kernels.  Errors: FDFB_ENOMEM, FDFB_EDEVICE. */
+int fdfb_prepare(fdfb_ctx *ctx, uint32_t flags);
 
 /*
  * Several functions of one input (Sec. "Application of Functional
@@ -169,18 +186,70 @@ typedef struct fdfb_job {
 } fdfb_job;
 
 /*
- * Bootstrap several jobs (mixed parameter sets and lookup tables) as one
- * stream-ordered submission.  Equivalent, output for output, to calling
- * fdfb_bootstrap_batch on each job, in order on `stream`; every job is
- * validated before anything is enqueued.  Errors as fdfb_bootstrap_batch.
+ * Bootstrap several jobs (mixed parameter sets, ring degrees and lookup
+ * tables; up to 256 jobs) as one stream-ordered submission, phase by phase
+ * (Fig. 2's steps for all jobs together).  The blind rotations of every job
+ * in the default (Karatsuba) form whose geometry the persistent kernel takes
+ * (N = 1024 with gadget 2^7 x 3 or N = 256 with 2^8 x 2, together with
+ * N = 2048 with 2^10 x 2 or 2^7 x 4) run in one persistent work-queue launch
+ * per phase and pair of geometries (16 jobs per launch): resident
+ * workgroups pull (job, accumulators) items from a device counter until
+ * the queue is empty.  Other jobs rotate in their own launches.  The queue
+ * is used when eligible jobs span more than one context (a single context's
+ * rotations already fill the device).  Outputs are bit-identical to
+ * fdfb_bootstrap_batch on each job.  Every job is validated before anything
+ * is enqueued.  Scratch: one block per context and stream, each job of the
+ * context at its own offset.  Errors as fdfb_bootstrap_batch, and
+ * FDFB_EINVAL for more than 256 jobs.
  */
 int fdfb_bootstrap_multi(const fdfb_job *jobs, uint32_t njobs, void *stream);
+
+/* fdfb_bootstrap_multi with the rotation form chosen by the caller:
+ * use_queue = 1 puts every eligible job in the persistent queue, 0 rotates
+ * each job in its own launches, -1 is fdfb_bootstrap_multi's rule.  The
+ * outputs are the same bits either way. */
+int fdfb_bootstrap_multi_ex(const fdfb_job *jobs, uint32_t njobs, int use_queue, void *stream);
+
+/*
+ * A multi-job submission captured once into a HIP graph and replayed with one
+ * launch (hipGraphLaunch): the whole bootstrap of every job, with the
+ * persistent work-queue rotations (use_queue as in fdfb_bootstrap_multi_ex).
+ * The graph owns its scratch (allocated here); the jobs' buffers, contexts
+ * and registered tables must stay valid while the graph exists, and each
+ * replay reads the jobs' inputs and writes their outputs at the pointers
+ * given here.  Creation runs the submission once eagerly on a private stream
+ * (setting every kernel's attributes) before capturing it, so the outputs
+ * are written by then.  Replays of one graph must not overlap each other
+ * (they share its scratch).  Errors: as fdfb_bootstrap_multi, FDFB_EDEVICE
+ * when capture or instantiation fails.
+ */
+typedef struct fdfb_graph fdfb_graph;
+int fdfb_multi_graph_create(const fdfb_job *jobs, uint32_t njobs, int use_queue, fdfb_graph **out);
+/* Replay the graph on `stream` (one graph launch).  FDFB_EABORTED if a job's
+ * context has its abort flag raised. */
+int fdfb_graph_launch(fdfb_graph *graph, void *stream);
+/* Whether the graph's rotations use the persistent queue, and its scratch bytes. */
+int fdfb_graph_info(const fdfb_graph *graph, uint32_t *uses_queue, size_t *scratch_bytes);
+/* Wait for the device, then release the graph and its scratch (NULL is a no-op). */
+void fdfb_graph_free(fdfb_graph *graph);
 
 /*
  * LWE -> LWE key switch with ksK (App. A Fig. "KeySwitch"):
  * d_in uint32[B][N+1] under s_F -> d_out uint32[B][n+1] under s.
  */
 int fdfb_keyswitch(fdfb_ctx *ctx, const uint32_t *d_in, uint32_t B, uint32_t *d_out, void *stream);
+
+/* Free every scratch block of the context, current and replaced (waits for
+ * the whole device first).  HIP graphs that captured calls on this context
+ * must not be replayed afterwards: their scratch is gone. */
+int fdfb_release_scratch(fdfb_ctx *ctx);
+
+/* Device error bits of the context (FDFB_DEVERR_*), set by kernels on
+ * invalid data found on the device (e.g. an unregistered lut_id).  Waits for
+ * the whole device, stores the bits in *bits and clears them if `clear`.
+ * Errors: FDFB_EINVAL on null pointers, FDFB_EDEVICE. */
+#define FDFB_DEVERR_LUT_ID 0x1u
+int fdfb_device_errors(fdfb_ctx *ctx, int clear, uint32_t *bits);
 
 /* ---- single procedures of the path, for tests and custom pipelines ----- */
 
@@ -231,6 +300,13 @@ int fdfb_pubmux(fdfb_ctx *ctx, const uint32_t *d_rlwe, const uint32_t *d_ctN,
 int fdfb_affine(const int32_t *d_W, const uint32_t *d_in, uint32_t rows, uint32_t cols, uint32_t width,
                 uint32_t *d_out, void *stream);
 
+/* Pairwise linear combination of LWE samples (same Lemma):
+ * d_out[b] = wx d_x[b] + wy d_y[b] (mod 2^32), coordinate-wise, for B
+ * samples of `width` words each (d_x and d_y may alias).  Needs no context.
+ * Errors: FDFB_EINVAL for null buffers or B * width >= 2^32. */
+int fdfb_lincomb2(const uint32_t *d_x, const uint32_t *d_y, int32_t wx, int32_t wy, uint32_t B, uint32_t width,
+                  uint32_t *d_out, void *stream);
+
 /* ---- debug helpers (host memory, use the secret keys) ------------------ */
 
 /* Encrypt B messages m[b] in [0, t) under s: b = <a, s> + Delta m + e with a
@@ -253,14 +329,22 @@ int fdfb_decrypt_debug(fdfb_ctx *ctx, const uint32_t *cts_host, uint32_t B, uint
  */
 int fdfb_export_keys(const fdfb_ctx *ctx, void *buf, size_t *len);
 
-/* Rebuild a context from fdfb_export_keys output.  Errors: FDFB_EINVAL for
- * a malformed or truncated buffer. */
+/* Rebuild a context from fdfb_export_keys output.  Every section length is
+ * checked against the parameters and against the bytes present before any
+ * copy.  Errors: FDFB_EINVAL for a wrong magic, unsupported parameters,
+ * inconsistent or truncated sections, non-binary secrets or table values
+ * >= t; FDFB_ENOMEM. */
 int fdfb_import_keys(const void *buf, size_t len, fdfb_ctx **out);
 
 /* Copy one raw key array to host memory (for key-equality checks):
  * which = 0 s [n], 1 s_F [N], 2 brK [n][2 g_ell][2][N], 3 pK [N][pk_ell][2][N],
  * 4 ksK [N][ks_ell][n+1].  *count: in = capacity (words), out = words needed. */
 int fdfb_get_key(const fdfb_ctx *ctx, uint32_t which, uint32_t *host, size_t *count);
+
+/* Copy the rotation polynomials of a registered table to host memory:
+ * host int32[2][N] = rotP_0, rotP_1 (unscaled table values, Sec. 3.3).
+ * Errors: FDFB_EINVAL for a null pointer or an unknown lut_id. */
+int fdfb_get_rotation_polys(const fdfb_ctx *ctx, int32_t lut_id, int32_t *host);
 
 /* ---- serving engine ----------------------------------------------------- */
 
@@ -272,36 +356,45 @@ int fdfb_get_key(const fdfb_ctx *ctx, uint32_t which, uint32_t *host, size_t *co
  * and the later ones that share its context and flags, in arrival order (at
  * most max_batch samples), admits it only
  * if its device scratch fits in the memory budget next to the batches in
- * flight (a batch is always admitted when nothing is in flight), gathers the
- * inputs, bootstraps them and scatters the outputs.  Batches on different
- * streams overlap on the device.  Each output is bit-identical to a
- * standalone fdfb_bootstrap_batch of that request.
- * While a server runs, its contexts must not be used directly, and every
- * table must be registered before fdfb_server_create.
+ * flight, gathers the inputs, bootstraps them and scatters the outputs.
+ * Memory admission: the server owns one device arena of mem_budget bytes;
+ * every batch carves its staging buffers and bootstrap scratch from it
+ * (first fit) and returns them when it retires, so mem_budget bounds the
+ * device memory serving uses besides the contexts' keys.  A batch that does
+ * not fit is shortened to the longest prefix of its requests that does, or
+ * waits for running batches to retire.  Batches on different streams
+ * overlap on the device.  Each output is bit-identical to a standalone
+ * fdfb_bootstrap_batch of that request.  A failure fails the requests of
+ * its batch only.  Contexts may still be used directly (calls take the
+ * context's lock) and tables may be registered at any time.
  */
 typedef struct fdfb_server fdfb_server;
 
 typedef struct fdfb_serving_stats {
     uint64_t requests_done, bootstraps_done, batches;
-    uint64_t max_in_flight_bytes; /* peak admitted scratch */
+    uint64_t max_in_flight_bytes; /* peak admitted bytes (staging + scratch) */
+    uint64_t arena_bytes;         /* size of the admission arena */
     double seconds;               /* since creation */
 } fdfb_serving_stats;
 
 /* ctxs[nctx]: parameter sets served (requests name them by index);
  * max_batch: largest batch (and request) in samples; mem_budget: bytes of
- * device scratch admitted at once; nstreams: 1..8 device streams.
- * Allocates the staging buffers and uploads keys.  Errors: FDFB_EINVAL,
- * FDFB_ENOMEM, FDFB_EDEVICE. */
+ * the admission arena (at least one batch of max_batch samples of every
+ * context, else FDFB_EINVAL with the size needed in fdfb_last_error);
+ * nstreams: 1..8 device streams.  Uploads keys and allocates the arena.
+ * Errors: FDFB_EINVAL, FDFB_ENOMEM, FDFB_EDEVICE. */
 int fdfb_server_create(fdfb_ctx *const *ctxs, uint32_t nctx, uint32_t max_batch, size_t mem_budget,
                        uint32_t nstreams, fdfb_server **out);
 
 /* Enqueue a request of B samples (1 <= B <= max_batch) of context ctx_index:
  * same buffers and flags as fdfb_bootstrap_batch, device memory owned by the
- * caller and untouched until the request completes.  Thread-safe; returns
- * at once with *req_id. */
+ * caller.  The inputs are read only after the work enqueued on `stream`
+ * before this call (an event recorded here), so they may still be being
+ * produced there; outputs are written before the request completes and must
+ * not be touched until then.  Thread-safe; returns at once with *req_id. */
 int fdfb_server_submit(fdfb_server *srv, uint32_t ctx_index, const uint32_t *d_cts,
                        const int32_t *d_lut_ids, uint32_t B, uint32_t *d_out, uint32_t flags,
-                       uint64_t *req_id);
+                       void *stream, uint64_t *req_id);
 
 /* *done = 1 once the request's outputs are in place (0 while pending). */
 int fdfb_server_poll(fdfb_server *srv, uint64_t req_id, int *done);
@@ -314,6 +407,62 @@ int fdfb_server_stats(fdfb_server *srv, fdfb_serving_stats *out);
 
 /* Finish the waiting and running requests, then release the server. */
 void fdfb_server_destroy(fdfb_server *srv);
+
+/* ---- autotuning of the blind rotation ----------------------------------- */
+
+/*
+ * How a batched blind rotation of A accumulators is issued.  form:
+ *   FDFB_FORM_AUTO   the fixed rule by launch round size
+ *   FDFB_FORM_1W     one wavefront per accumulator, all three Karatsuba
+ *                    products at once (four wavefronts per accumulator at
+ *                    N = 2048)
+ *   FDFB_FORM_1W2    one wavefront per accumulator, two per SIMD, products
+ *                    one after another (N = 1024, gadget 2^7 x 3)
+ *   FDFB_FORM_2W     two wavefronts per accumulator (N = 1024, gadget 2^7 x 3)
+ *   FDFB_FORM_QUEUE  the persistent work-queue kernel, one launch
+ * round: accumulators per launch round (0 = the form's resident capacity;
+ * ignored by the queue).  ms: measured milliseconds per rotation (0 if none).
+ * Every plan gives the same output bits.
+ */
+#define FDFB_FORM_AUTO 0u
+#define FDFB_FORM_1W 1u
+#define FDFB_FORM_1W2 2u
+#define FDFB_FORM_2W 3u
+#define FDFB_FORM_QUEUE 4u
+typedef struct fdfb_br_plan {
+    uint32_t form, round;
+    double ms;
+} fdfb_br_plan;
+
+/* The plans the kernels offer for the context's geometry.  *count: in =
+ * capacity of plans (may be 0 with plans = NULL), out = number of plans.
+ * Errors: FDFB_ENOTSUP without a batched rotation, FDFB_EINVAL when the
+ * buffer is too small (*count then holds the number needed). */
+int fdfb_br_plans(fdfb_ctx *ctx, fdfb_br_plan *plans, uint32_t *count);
+
+/* Time every plan on A accumulators (per accumulators per sample, random
+ * contents, the context's keys), each once to warm up and then `reps` times
+ * on a private stream, and record the fastest for (this device's compute
+ * units, N, ell, digit chunks, n, A) in the process-wide table; later
+ * rotations of that size and geometry use it (every entry point, every
+ * context with the same geometry).  With the environment variable
+ * FDFB_TUNE_CACHE set to a path, the table is read from that file at first
+ * use and written back after each tuning run.  *best receives the chosen
+ * plan and its time; tried (nullable, capacity *ntried) every plan timed.
+ * Allocates and frees timing buffers; synchronises its stream.
+ * Errors: FDFB_EINVAL, FDFB_ENOTSUP, FDFB_ENOMEM, FDFB_EDEVICE. */
+int fdfb_autotune(fdfb_ctx *ctx, uint32_t A, uint32_t per, uint32_t reps, fdfb_br_plan *best,
+                  fdfb_br_plan *tried, uint32_t *ntried);
+
+/* Record a plan for A accumulators of the context's geometry (plan = NULL
+ * removes the entry, back to the fixed rule), or read the plan in use. */
+int fdfb_br_set_plan(fdfb_ctx *ctx, uint32_t A, const fdfb_br_plan *plan);
+int fdfb_br_get_plan(fdfb_ctx *ctx, uint32_t A, fdfb_br_plan *plan);
+
+/* Write the table to a file / merge a file into it / empty it. */
+int fdfb_tune_save(const char *path);
+int fdfb_tune_load(const char *path);
+int fdfb_tune_clear(void);
 
 /* ---- per-phase device timing ------------------------------------------- */
 
@@ -343,8 +492,9 @@ int fdfb_profile_read(fdfb_ctx *ctx, double *ms, uint32_t *calls);
 /* Number of kernel launches one batched blind rotation of `accumulators`
  * accumulators (`per_ct` consecutive ones per ciphertext, 1 <= per_ct)
  * takes on the current device, for matching per-launch profiles: the MFMA
- * form is issued in rounds of the device's resident workgroup capacity, the
- * plain and direct forms in one launch.  0 accumulators take 0 launches.
+ * form is issued in rounds of the device's resident workgroup capacity (or
+ * of the tuned plan's round size; a queue plan is one launch), the plain and
+ * direct forms in one launch.  0 accumulators take 0 launches.
  * FDFB_EINVAL on a null pointer or per_ct = 0, FDFB_EDEVICE on a HIP error. */
 int fdfb_br_launches(fdfb_ctx *ctx, uint32_t accumulators, uint32_t per_ct, uint32_t flags,
                      uint32_t *launches);

@@ -47,7 +47,14 @@ class _Params(C.Structure):
 
 class _ServerStats(C.Structure):
     _fields_ = [("requests_done", C.c_uint64), ("bootstraps_done", C.c_uint64), ("batches", C.c_uint64),
-                ("max_in_flight_bytes", C.c_uint64), ("seconds", C.c_double)]
+                ("max_in_flight_bytes", C.c_uint64), ("arena_bytes", C.c_uint64), ("seconds", C.c_double)]
+
+
+class _Plan(C.Structure):
+    _fields_ = [("form", C.c_uint32), ("round", C.c_uint32), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {"form": FORMS.get(self.form, self.form), "round": self.round, "ms": self.ms}
 
 
 class _Job(C.Structure):
@@ -63,8 +70,16 @@ EXPORTED = [
     "fdfb_export_keys", "fdfb_import_keys", "fdfb_get_key", "fdfb_profile", "fdfb_profile_read",
     "fdfb_br_launches", "fdfb_measure_mfma_peak", "fdfb_set_abort", "fdfb_free", "fdfb_last_error",
     "fdfb_server_create", "fdfb_server_submit", "fdfb_server_poll", "fdfb_server_wait",
-    "fdfb_server_stats", "fdfb_server_destroy", "fdfb_affine",
+    "fdfb_server_stats", "fdfb_server_destroy", "fdfb_affine", "fdfb_lincomb2", "fdfb_prepare",
+    "fdfb_release_scratch", "fdfb_device_errors",
+    "fdfb_bootstrap_multi_ex", "fdfb_multi_graph_create", "fdfb_graph_launch", "fdfb_graph_info",
+    "fdfb_graph_free", "fdfb_br_plans", "fdfb_autotune", "fdfb_br_set_plan", "fdfb_br_get_plan",
+    "fdfb_tune_save", "fdfb_tune_load", "fdfb_tune_clear", "fdfb_get_rotation_polys",
 ]
+
+FORMS = {0: "auto", 1: "1w", 2: "1w2", 3: "2w", 4: "queue"}
+
+DEVERR_LUT_ID = 0x1
 
 PHASES = ["modswitch_init", "sign_br", "extract_bits", "packing_ks", "pubmux", "function_br", "output"]
 
@@ -86,6 +101,19 @@ def lib():
             "fdfb_bootstrap_multi_lut": (i, [P, P, P, u32, u32, P, u32, P]),
             "fdfb_tfhe_bootstrap_batch": (i, [P, P, P, u32, P, u32, P]),
             "fdfb_bootstrap_multi": (i, [P, u32, P]),
+            "fdfb_bootstrap_multi_ex": (i, [P, u32, i, P]),
+            "fdfb_multi_graph_create": (i, [P, u32, i, P]),
+            "fdfb_graph_launch": (i, [P, P]),
+            "fdfb_graph_info": (i, [P, P, C.POINTER(sz)]),
+            "fdfb_graph_free": (None, [P]),
+            "fdfb_br_plans": (i, [P, P, P]),
+            "fdfb_autotune": (i, [P, u32, u32, u32, P, P, P]),
+            "fdfb_br_set_plan": (i, [P, u32, P]),
+            "fdfb_br_get_plan": (i, [P, u32, P]),
+            "fdfb_tune_save": (i, [C.c_char_p]),
+            "fdfb_tune_load": (i, [C.c_char_p]),
+            "fdfb_tune_clear": (i, []),
+            "fdfb_get_rotation_polys": (i, [P, C.c_int32, P]),
             "fdfb_keyswitch": (i, [P, P, u32, P, P]),
             "fdfb_modswitch": (i, [P, P, u32, P, P]),
             "fdfb_blind_rotate": (i, [P, P, P, u32, u32, u32, P]),
@@ -105,12 +133,16 @@ def lib():
             "fdfb_free": (None, [P]),
             "fdfb_last_error": (C.c_char_p, []),
             "fdfb_server_create": (i, [P, u32, u32, sz, u32, P]),
-            "fdfb_server_submit": (i, [P, u32, P, P, u32, P, u32, P]),
+            "fdfb_server_submit": (i, [P, u32, P, P, u32, P, u32, P, P]),
             "fdfb_server_poll": (i, [P, C.c_uint64, P]),
             "fdfb_server_wait": (i, [P, C.c_uint64, P]),
             "fdfb_server_stats": (i, [P, P]),
             "fdfb_server_destroy": (None, [P]),
             "fdfb_affine": (i, [P, P, u32, u32, u32, P, P]),
+            "fdfb_lincomb2": (i, [P, P, C.c_int32, C.c_int32, u32, u32, P, P]),
+            "fdfb_prepare": (i, [P, u32]),
+            "fdfb_release_scratch": (i, [P]),
+            "fdfb_device_errors": (i, [P, i, P]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -200,6 +232,12 @@ class Context:
         _check(lib().fdfb_get_key(self._h, which, _np_ptr(out), C.byref(n)))
         return out
 
+    def rotation_polys(self, lut_id: int):
+        """rotP_0, rotP_1 of a registered table (int32 [N] each)."""
+        out = np.empty(2 * self.params.N, np.int32)
+        _check(lib().fdfb_get_rotation_polys(self._h, lut_id, _np_ptr(out)))
+        return out[: self.params.N], out[self.params.N:]
+
     def register_lut(self, table) -> int:
         tab = np.ascontiguousarray(table, dtype=np.uint32)
         lid = C.c_int32()
@@ -236,8 +274,54 @@ class Context:
         _check(lib().fdfb_br_launches(self._h, accumulators, per_ct, flags, C.byref(n)))
         return n.value
 
+    # ---- autotuning of the blind rotation ---------------------------------
+    def br_plans(self) -> list:
+        """Every issue plan (form, round) the kernels offer for this geometry."""
+        n = C.c_uint32(0)
+        _check(lib().fdfb_br_plans(self._h, None, C.byref(n)))
+        arr = (_Plan * n.value)()
+        _check(lib().fdfb_br_plans(self._h, arr, C.byref(n)))
+        return [(p.form, p.round) for p in arr]
+
+    def autotune(self, A: int, per: int = 1, reps: int = 2) -> dict:
+        """Time every plan on A accumulators and record the fastest for this
+        geometry and size; returns the choice and every timing."""
+        best = _Plan()
+        cap = 16
+        tried = (_Plan * cap)()
+        n = C.c_uint32(cap)
+        _check(lib().fdfb_autotune(self._h, A, per, reps, C.byref(best), tried, C.byref(n)))
+        return {"best": best.as_dict(), "tried": [tried[k].as_dict() for k in range(min(n.value, cap))]}
+
+    def set_plan(self, A: int, form=None, round: int = 0):
+        """Force the plan for A accumulators (form None: back to the fixed rule)."""
+        if form is None:
+            _check(lib().fdfb_br_set_plan(self._h, A, None))
+        else:
+            p = _Plan(form, round, 0.0)
+            _check(lib().fdfb_br_set_plan(self._h, A, C.byref(p)))
+
+    def get_plan(self, A: int) -> dict:
+        p = _Plan()
+        _check(lib().fdfb_br_get_plan(self._h, A, C.byref(p)))
+        return p.as_dict()
+
     def set_abort(self, raised: bool):
         lib().fdfb_set_abort(self._h, 1 if raised else 0)
+
+    def prepare(self, flags: int = 0):
+        """Upload keys, tables and the requested form without enqueuing work."""
+        _check(lib().fdfb_prepare(self._h, flags))
+
+    def release_scratch(self):
+        """Free every scratch block (waits for the device)."""
+        _check(lib().fdfb_release_scratch(self._h))
+
+    def device_errors(self, clear: bool = True) -> int:
+        """Device error bits (DEVERR_*) since the last clear; waits for the device."""
+        bits = C.c_uint32()
+        _check(lib().fdfb_device_errors(self._h, 1 if clear else 0, C.byref(bits)))
+        return bits.value
 
     # ---- device entry points (torch tensors) ------------------------------
     def bootstrap_multi_lut(self, cts, lut_ids, out, flags: int = 0, stream=None):
@@ -303,10 +387,13 @@ class Server:
         _check(lib().fdfb_server_create(arr, len(self.ctxs), max_batch, mem_budget, nstreams, C.byref(h)))
         self._h = h
 
-    def submit(self, ctx_index: int, cts, lut_ids, out, flags: int = 0) -> int:
+    def submit(self, ctx_index: int, cts, lut_ids, out, flags: int = 0, stream=None) -> int:
+        """Queue a request; its inputs are read after the work already queued on
+        `stream` (the current torch stream by default)."""
         rid = C.c_uint64()
         _check(lib().fdfb_server_submit(self._h, ctx_index, _dev_ptr(cts, "cts"), _dev_ptr(lut_ids, "lut_ids"),
-                                        int(cts.shape[0]), _dev_ptr(out, "out"), flags, C.byref(rid)))
+                                        int(cts.shape[0]), _dev_ptr(out, "out"), flags, _stream(stream),
+                                        C.byref(rid)))
         return rid.value
 
     def poll(self, rid: int) -> bool:
@@ -344,13 +431,76 @@ def affine(W, cts, out, stream=None):
     return out
 
 
-def bootstrap_multi(jobs, stream=None):
-    """jobs: list of (Context, cts, lut_ids, out, flags)."""
+def lincomb2(x, y, wx: int, wy: int, out, stream=None):
+    """out = wx * x + wy * y mod 2^32, sample by sample (x, y, out [B][width])."""
+    B, width = int(x.shape[0]), int(x.shape[1])
+    if tuple(y.shape) != (B, width) or tuple(out.shape) != (B, width):
+        raise ValueError("x, y and out must have the same shape")
+    _check(lib().fdfb_lincomb2(_dev_ptr(x, "x"), _dev_ptr(y, "y"), wx, wy, B, width, _dev_ptr(out, "out"),
+                               _stream(stream)))
+    return out
+
+
+def _jobs(jobs):
     arr = (_Job * max(1, len(jobs)))()
     for k, (ctx, cts, ids, out, flags) in enumerate(jobs):
         arr[k] = _Job(ctx._h, _dev_ptr(cts, "cts").value, _dev_ptr(ids, "lut_ids").value, int(cts.shape[0]),
                       _dev_ptr(out, "out").value, flags)
-    _check(lib().fdfb_bootstrap_multi(arr, len(jobs), _stream(stream)))
+    return arr
+
+
+def bootstrap_multi(jobs, stream=None, use_queue=None):
+    """jobs: list of (Context, cts, lut_ids, out, flags).  use_queue: None for
+    the library's rule, True / False to force the persistent work-queue
+    rotations on or off (same output bits)."""
+    arr = _jobs(jobs)
+    if use_queue is None:
+        _check(lib().fdfb_bootstrap_multi(arr, len(jobs), _stream(stream)))
+    else:
+        _check(lib().fdfb_bootstrap_multi_ex(arr, len(jobs), 1 if use_queue else 0, _stream(stream)))
+
+
+class MultiGraph:
+    """A multi-job submission captured into a HIP graph (fdfb_multi_graph_create):
+    replay() runs every job's bootstrap with one graph launch."""
+
+    def __init__(self, jobs, use_queue=None):
+        self._keep = list(jobs)  # contexts and tensors must outlive the graph
+        h = C.c_void_p()
+        q = -1 if use_queue is None else (1 if use_queue else 0)
+        _check(lib().fdfb_multi_graph_create(_jobs(jobs), len(jobs), q, C.byref(h)))
+        self._h = h
+
+    def replay(self, stream=None):
+        _check(lib().fdfb_graph_launch(self._h, _stream(stream)))
+
+    def info(self) -> dict:
+        q, b = C.c_uint32(), C.c_size_t()
+        _check(lib().fdfb_graph_info(self._h, C.byref(q), C.byref(b)))
+        return {"uses_queue": bool(q.value), "scratch_bytes": b.value}
+
+    def close(self):
+        if self._h:
+            lib().fdfb_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune_save(path: str):
+    _check(lib().fdfb_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check(lib().fdfb_tune_load(path.encode()))
+
+
+def tune_clear():
+    _check(lib().fdfb_tune_clear())
 
 
 def to_device(a: np.ndarray, device="cuda"):

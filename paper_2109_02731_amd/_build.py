@@ -20,7 +20,8 @@ HIP_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, "host.cpp"), os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "kernels.hip")]
+    srcs = [os.path.join(CSRC, "host.cpp"), os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "tune.cpp"),
+            os.path.join(CSRC, "kernels.hip")]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *srcs,
            "-lpthread"]

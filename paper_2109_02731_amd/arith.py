@@ -6,27 +6,22 @@ maps (Sec. "Application of Functional Bootstrapping"):
   taken on the integer lift of s: exact, since x + y and x - y have the
   same parity.  Two bootstraps per pair, issued as one batch.
 
-Every step runs in the library's kernels (``fdfb_affine``,
-``fdfb_bootstrap_batch``); this module only builds the integer weight
-matrices and tables.  Both need x, y in [0, t/2) (t = 2^log2_t): then
-x - y is read correctly as a two's-complement value of Z_t and x + y < t;
-the product is returned mod t.  The Chinese-remainder
-plaintext extension the same section describes needs pairwise coprime
-moduli, which t | 2^32 excludes at q = 2^32.
+Every step runs in the library's kernels (``fdfb_lincomb2``,
+``fdfb_bootstrap_batch``); this module only picks the weights and builds
+the tables.  Both need x, y in [0, t/2) (t = 2^log2_t): then x - y is read
+correctly as a two's-complement value of Z_t and x + y < t; the product is
+returned mod t.  The Chinese-remainder plaintext extension of the same
+section needs pairwise coprime moduli t_i, so all but one would be odd; an
+odd t_i does not divide q = 2^32, so Delta t_i is not 0 mod q and the public
+mux could no longer decompose (p_B - p_A) mod t_i alone: it would need the
+full-width digits of Delta (p_B - p_A), ceil(32 / log2 L_boot) sign
+rotations instead of ceil(log2 t / log2 L_boot).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import affine
-
-
-def _stack_weights(B: int, sign: int):
-    """[I | sign*I] as int32 [B][2B]."""
-    W = np.zeros((B, 2 * B), np.int32)
-    W[np.arange(B), np.arange(B)] = 1
-    W[np.arange(B), B + np.arange(B)] = sign
-    return W
+from . import lincomb2
 
 
 def relu_table(t: int) -> np.ndarray:
@@ -57,29 +52,24 @@ class Arith:
         self.qs, self.qd = ctx.register_lut(qs), ctx.register_lut(qd)
         self._torch = torch
 
-    def _affine(self, W: np.ndarray, cts):
-        torch = self._torch
-        out = torch.empty((W.shape[0], cts.shape[1]), dtype=torch.int32, device=cts.device)
-        affine(torch.from_numpy(W).to(cts.device), cts, out)
-        return out
+    def _lin(self, x, y, wx: int, wy: int):
+        out = self._torch.empty_like(x)
+        return lincomb2(x, y, wx, wy, out)
 
     def maximum(self, x, y):
         torch = self._torch
         B = int(x.shape[0])
-        xy = torch.cat([x, y])
-        d = self._affine(_stack_weights(B, -1), xy)  # x - y
+        d = self._lin(x, y, 1, -1)  # x - y
         r = torch.empty_like(d)
         self.ctx.bootstrap_batch(d, torch.full((B,), self.relu, dtype=torch.int32, device=x.device), r)
-        return self._affine(_stack_weights(B, 1), torch.cat([r, y]))  # relu(x - y) + y
+        return self._lin(r, y, 1, 1)  # relu(x - y) + y
 
     def multiply(self, x, y):
         torch = self._torch
         B = int(x.shape[0])
-        xy = torch.cat([x, y])
-        W = np.concatenate([_stack_weights(B, 1), _stack_weights(B, -1)])  # [x + y; x - y]
-        sd = self._affine(W, xy)
+        sd = torch.cat([self._lin(x, y, 1, 1), self._lin(x, y, 1, -1)])  # [x + y; x - y]
         ids = torch.cat([torch.full((B,), self.qs, dtype=torch.int32, device=x.device),
                          torch.full((B,), self.qd, dtype=torch.int32, device=x.device)])
         q = torch.empty_like(sd)
         self.ctx.bootstrap_batch(sd, ids, q)
-        return self._affine(_stack_weights(B, -1), q)  # q(x + y) - q(x - y)
+        return self._lin(q[:B], q[B:], 1, -1)  # q(x + y) - q(x - y)

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "kernels.h"
 
@@ -92,8 +93,9 @@ __global__ void k_extract(const uint32_t *__restrict__ acc, uint32_t *__restrict
 // Key switching (App. A Fig. "KeySwitch"), LWE(din) -> GLWE flattened to
 // out_len words:  out = [b, 0, ...] - sum_i sum_j Decomp(a_i)_j K[i][j].
 // Workgroup: KS_TB samples x 256 output words.  The samples' digits of one
-// chunk of input coordinates are staged in LDS; each key word is read once
-// per workgroup and used for all KS_TB samples.
+// chunk of input coordinates are staged in LDS (16 bits each: bases up to
+// 2^16); each key word is read once per workgroup and used for all KS_TB
+// samples.
 // ---------------------------------------------------------------------------
 constexpr int KS_TB = 16;
 constexpr int KS_CHUNK = 128;
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(256) void k_keyswitch(const uint32_t *__restrict__ 
                                                    int log2B, int ell, uint32_t out_len,
                                                    uint32_t *__restrict__ out)
 {
-    __shared__ uint8_t dig[KS_CHUNK * 8 * KS_TB];  // [coord][j][sample], ell <= 8
+    __shared__ uint16_t dig[KS_CHUNK * 8 * KS_TB];  // [coord][j][sample], ell <= 8
     const uint32_t w = blockIdx.x * 256 + threadIdx.x;
     const uint32_t b0 = blockIdx.y * KS_TB;
     const uint32_t drop = 32 - ell * log2B;
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(256) void k_keyswitch(const uint32_t *__restrict__ 
             for (uint32_t ii = 0; ii < cnt; ++ii) {
                 for (int j = 0; j < ell; ++j) {
                     const uint32_t k = key[((size_t)(i0 + ii) * ell + j) * out_len + w];
-                    const uint8_t *dg = dig + (ii * 8 + j) * KS_TB;
+                    const uint16_t *dg = dig + (ii * 8 + j) * KS_TB;
 #pragma unroll
                     for (int c = 0; c < KS_TB; ++c) acc[c] += (uint32_t)dg[c] * k;
                 }
@@ -267,6 +269,16 @@ __global__ __launch_bounds__(256) void k_affine(const int32_t *__restrict__ W, c
         if (r0 + r < rows) out[(size_t)(r0 + r) * width + k] = acc[r];
 }
 
+// Two-term linear combination of LWE samples (the same Lemma): out = wx x + wy y,
+// word by word; x and y may be the same buffer.
+__global__ __launch_bounds__(256) void k_lincomb2(const uint32_t *__restrict__ x, const uint32_t *__restrict__ y,
+                                                  uint32_t wx, uint32_t wy, uint32_t count,
+                                                  uint32_t *__restrict__ out)
+{
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k < count) out[k] = wx * x[k] + wy * y[k];
+}
+
 // ---------------------------------------------------------------------------
 // PubMux of the bootstrap (Sec. 3.1 Fig. 1 with the selection of Fig. 2):
 //   p_A = rotP_1 X^{b_N}, p_B = rotP_0 X^{b_N}, delta = (p_B - p_A) mod t,
@@ -278,8 +290,8 @@ __global__ __launch_bounds__(256) void k_pubmux(const uint32_t *__restrict__ rlw
                                                 const uint32_t *__restrict__ ctN,
                                                 const int32_t *__restrict__ lut_ids,
                                                 const int32_t *__restrict__ luts, int nluts,
-                                                uint32_t *__restrict__ acc, int n, int N,
-                                                int log2_t, int boot_log2B, int ellb, uint32_t per)
+                                                uint32_t *__restrict__ err, uint32_t *__restrict__ acc, int n,
+                                                int N, int log2_t, int boot_log2B, int ellb, uint32_t per)
 {
     extern __shared__ uint8_t smem[];
     int8_t *dx = (int8_t *)smem;                              // [ellb][2N]
@@ -288,7 +300,8 @@ __global__ __launch_bounds__(256) void k_pubmux(const uint32_t *__restrict__ rlw
     const uint32_t b = eidx / per;
     const int id = lut_ids[eidx];
     uint32_t *o = acc + (size_t)eidx * 2 * N;
-    if (id < 0 || id >= nluts) {  // unknown table: defined, all-zero output
+    if (id < 0 || id >= nluts) {  // unknown table: all-zero output, reported in *err
+        if (threadIdx.x == 0) atomicOr(err, 1u);
         for (int m = threadIdx.x; m < 2 * N; m += blockDim.x) o[m] = 0;
         return;
     }
@@ -333,11 +346,12 @@ __global__ __launch_bounds__(256) void k_pubmux(const uint32_t *__restrict__ rlw
 // X^{b_N}, 0] for the table of each sample (zero for an unknown table).
 // ---------------------------------------------------------------------------
 __global__ void k_init_tfhe(const uint32_t *__restrict__ ctN, const int32_t *__restrict__ lut_ids,
-                            const int32_t *__restrict__ luts, int nluts, uint32_t *__restrict__ acc, int n,
-                            int N, int log2_t)
+                            const int32_t *__restrict__ luts, int nluts, uint32_t *__restrict__ err,
+                            uint32_t *__restrict__ acc, int n, int N, int log2_t)
 {
     const uint32_t b = blockIdx.y;
     const int id = lut_ids[b];
+    if ((id < 0 || id >= nluts) && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 1u);
     const uint32_t e = ctN[(size_t)b * (n + 1)];
     const uint32_t delta = 1u << (32 - log2_t);
     uint32_t *row = acc + (size_t)b * 2 * N;
@@ -724,16 +738,16 @@ __device__ __attribute__((always_inline)) inline void kara_rot4(const uint4 *src
     }
 }
 
+// One accumulator (row, 2N words) rotated by the whole workgroup (64 WAVES
+// threads), its ModSwitched coefficients a_1..a_n at crow; LDS at smem.
 template <int N, int ELL, int CH>
-__global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g,
-                                                    const uint32_t *__restrict__ ctN, uint32_t a_base,
-                                                    uint32_t accs_per_ct, int n,
-                                                    const v4i *__restrict__ bfrag,
-                                                    const uint32_t *__restrict__ corr, int log2B)
+__device__ __attribute__((always_inline)) inline void br_kara_run(uint8_t *smem, uint32_t *__restrict__ row,
+                                                                 const uint32_t *__restrict__ crow, int n,
+                                                                 const v4i *__restrict__ bfrag,
+                                                                 const uint32_t *__restrict__ corr, int log2B)
 {
     using G = BrKara<N, ELL, CH>;
     constexpr int M = G::M;
-    extern __shared__ uint8_t smem[];
     uint32_t *accL = (uint32_t *)smem;  // [2][N]: per component, even half then odd half
     uint32_t *digL = accL + 2 * N;      // [DSETS][RV][3 products][SEQ_WORDS]
     auto seq = [&](int set, int r, int p) { return digL + ((set * G::RV + r) * 3 + p) * G::SEQ_WORDS; };
@@ -742,13 +756,10 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int jc = wv / G::WPC;  // output component of this wavefront
     const int hw = wv % G::WPC;  // its half of the tiles / coefficients
-    const uint32_t a_idx = a_base + blockIdx.x;  // accumulator; sample a_idx / accs_per_ct
-    uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
     for (int x = threadIdx.x; x < 2 * N; x += 64 * G::WAVES) {
         const int m = x & (N - 1);
         accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)] = row[x];
     }
-    const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
     const uint32_t drop = 32 - ELL * log2B;
 
     // Output row i of a tile starting at m0, for key shift s, is coefficient
@@ -952,6 +963,19 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
         const int m = x & (N - 1);
         row[x] = accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)];
     }
+}
+
+template <int N, int ELL, int CH>
+__global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g,
+                                                    const uint32_t *__restrict__ ctN, uint32_t a_base,
+                                                    uint32_t accs_per_ct, int n,
+                                                    const v4i *__restrict__ bfrag,
+                                                    const uint32_t *__restrict__ corr, int log2B)
+{
+    extern __shared__ uint8_t smem[];
+    const uint32_t a_idx = a_base + blockIdx.x;  // accumulator; sample a_idx / accs_per_ct
+    br_kara_run<N, ELL, CH>(smem, acc_g + (size_t)a_idx * 2 * N,
+                            ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1, n, bfrag, corr, log2B);
 }
 
 // ---------------------------------------------------------------------------
@@ -1199,33 +1223,34 @@ __global__ __launch_bounds__(64, 1) void k_br_kara1w(uint32_t *__restrict__ acc_
 // block by block; two barriers per step.  It halves the time of a step for
 // rounds small enough to give every wavefront a SIMD of its own.
 // ---------------------------------------------------------------------------
-template <int N, int ELL, int CH, int WV>
-__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) void k_br_kara1w2(uint32_t *__restrict__ acc_g,
-                                                    const uint32_t *__restrict__ ctN, uint32_t a_base,
-                                                    uint32_t accs_per_ct, int n,
-                                                    const v4i *__restrict__ bfrag,
-                                                    const uint32_t *__restrict__ corr, int log2B)
+// One accumulator (row) rotated by WV wavefronts whose threads are numbered
+// tid = 0 .. 64 WV - 1, LDS at smem.  SKIP: steps with a_i = 0 are skipped
+// (their CMux adds exactly zero); without it every step runs, so that
+// wavefronts of one workgroup rotating different accumulators meet the same
+// barriers.  The result is stored only if `store`.
+template <int N, int ELL, int CH, int WV, bool SKIP>
+__device__ __attribute__((always_inline)) inline void br_kara1w2_run(uint8_t *smem, uint32_t *__restrict__ row,
+                                                                    const uint32_t *__restrict__ crow, int n,
+                                                                    const v4i *__restrict__ bfrag,
+                                                                    const uint32_t *__restrict__ corr, int log2B,
+                                                                    int tid, bool store)
 {
     using G = BrKara<N, ELL, CH>;
     static_assert(G::WPC == 1, "one wavefront per accumulator needs N <= 1024");
     constexpr int M = G::M;
-    extern __shared__ uint8_t smem[];
     uint32_t *accL = (uint32_t *)smem;  // [2][N]: per component, even half then odd half
     uint32_t *digL = accL + 2 * N;      // [RV][V_e (then V_e + V_o), V_o][SEQ_WORDS]
     auto seq = [&](int r, int p) { return digL + (r * 2 + (p & 1)) * G::SEQ_WORDS; };
 
     static_assert(WV == 1 || WV == 2, "one wavefront, or one per component's digit rows");
     constexpr int RW = G::RV / WV;  // digit rows per wavefront: those of component hw when WV = 2
-    const int lane = threadIdx.x & 63;
-    const int hw = WV == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int lane = tid & 63;
+    const int hw = WV == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r0 = hw * RW;  // first digit row of this wavefront
-    const uint32_t a_idx = a_base + blockIdx.x;  // accumulator; sample a_idx / accs_per_ct
-    uint32_t *row = acc_g + (size_t)a_idx * 2 * N;
-    for (int x = threadIdx.x; x < 2 * N; x += 64 * WV) {
+    for (int x = tid; x < 2 * N; x += 64 * WV) {
         const int m = x & (N - 1);
         accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)] = row[x];
     }
-    const uint32_t *crow = ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1;
     const uint32_t drop = 32 - ELL * log2B;
     const int ri = lane & 15, g = lane >> 4;
     const int S0 = M - 4 * ri + 16 * g;
@@ -1237,7 +1262,8 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     constexpr int JSTRIDE = G::NKB * 64;
     auto next_live = [&](int i) {
         int k = i + 1;
-        while (k < n && __builtin_amdgcn_readfirstlane(crow[k]) == 0) ++k;
+        if constexpr (SKIP)
+            while (k < n && __builtin_amdgcn_readfirstlane(crow[k]) == 0) ++k;
         return k;
     };
 
@@ -1479,10 +1505,90 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
         i = inext;
     }
     __syncthreads();
-    for (int x = threadIdx.x; x < 2 * N; x += 64 * WV) {
-        const int m = x & (N - 1);
-        row[x] = accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)];
+    if (store)
+        for (int x = tid; x < 2 * N; x += 64 * WV) {
+            const int m = x & (N - 1);
+            row[x] = accL[(x & ~(N - 1)) + (m & 1) * M + (m >> 1)];
+        }
+}
+
+template <int N, int ELL, int CH, int WV>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) void k_br_kara1w2(uint32_t *__restrict__ acc_g,
+                                                    const uint32_t *__restrict__ ctN, uint32_t a_base,
+                                                    uint32_t accs_per_ct, int n,
+                                                    const v4i *__restrict__ bfrag,
+                                                    const uint32_t *__restrict__ corr, int log2B)
+{
+    extern __shared__ uint8_t smem[];
+    const uint32_t a_idx = a_base + blockIdx.x;  // accumulator; sample a_idx / accs_per_ct
+    br_kara1w2_run<N, ELL, CH, WV, true>(smem, acc_g + (size_t)a_idx * 2 * N,
+                                         ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1, n, bfrag, corr,
+                                         log2B, (int)threadIdx.x, true);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent work-queue blind rotation: one launch rotates the accumulators
+// of several jobs (contexts with their own keys, tables and samples) of two
+// ring degrees at once.  Resident workgroups (4 wavefronts, two per CU) pull
+// items from a device counter until the queue is empty.  An item of a "wide"
+// job (N = 2048, geometry B) is one accumulator rotated by the whole
+// workgroup (br_kara_run); an item of a narrow job (geometry A, N <= 1024)
+// is four accumulators, one per wavefront (br_kara1w2_run), which run every
+// step so that all four meet the same barriers (a step with a_i = 0 adds
+// exactly zero).  A wavefront past the end of its job repeats the job's last
+// accumulator without storing it.  Wide items come first in the queue (the
+// longer items start first).  Results equal those of the per-job launches,
+// bit for bit.
+// ---------------------------------------------------------------------------
+template <int NA, int LA, int CA, int NB, int LB, int CB>
+struct BrQueueGeom {
+    using GA = BrKara<NA, LA, CA>;
+    using GB = BrKara<NB, LB, CB>;
+    static_assert(GA::WPC == 1 && GB::WAVES == 4, "narrow: one wavefront per accumulator; wide: four");
+    static constexpr size_t LDS_A = GA::LDS2W_BYTES;  // per wavefront
+    static constexpr size_t LDS = 4 * LDS_A > GB::LDS_BYTES ? 4 * LDS_A : GB::LDS_BYTES;
+};
+
+template <int NA, int LA, int CA, int NB, int LB, int CB>
+__global__ __launch_bounds__(256, 2) void k_br_queue(const BrQueue q, uint32_t *__restrict__ counter)
+{
+    using Q = BrQueueGeom<NA, LA, CA, NB, LB, CB>;
+    extern __shared__ uint8_t smem[];
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    for (;;) {
+        // the workgroup's next item, broadcast through LDS word 0 (free here:
+        // every wavefront has passed the last barrier of the previous item)
+        __syncthreads();
+        if (threadIdx.x == 0) *(volatile uint32_t *)smem = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)smem);
+        __syncthreads();
+        if (item >= q.items) break;  // uniform: every wavefront leaves
+        uint32_t j = 0;
+        while (j + 1 < q.njobs && item >= q.job[j + 1].first_item) ++j;
+        const BrQueueJob &J = q.job[j];
+        const uint32_t k = item - J.first_item;
+        const v4i *bfrag = (const v4i *)J.bfrag;
+        if (J.wide) {
+            br_kara_run<NB, LB, CB>(smem, J.acc + (size_t)k * 2 * NB, J.ctN + (size_t)(k / J.per) * (J.n + 1) + 1,
+                                    (int)J.n, bfrag, J.corr, (int)J.log2B);
+        } else {
+            uint32_t a = 4 * k + wave;
+            const bool store = a < J.accs;
+            if (!store) a = J.accs - 1;
+            br_kara1w2_run<NA, LA, CA, 1, false>(smem + wave * Q::LDS_A, J.acc + (size_t)a * 2 * NA,
+                                                 J.ctN + (size_t)(a / J.per) * (J.n + 1) + 1, (int)J.n, bfrag,
+                                                 J.corr, (int)J.log2B, (int)threadIdx.x & 63, store);
+        }
     }
+}
+
+// Fill n words with v (resets the queue counters; a kernel rather than a
+// memset so that it can sit in a captured HIP graph).
+__global__ void k_fill(uint32_t *__restrict__ p, uint32_t n, uint32_t v)
+{
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) p[x] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1588,11 +1694,11 @@ hipError_t launch_mfma_stream(uint32_t blocks, uint32_t iters, int32_t *out, hip
 }
 
 hipError_t launch_init_tfhe(const Geometry &G, const uint32_t *ctN, const int32_t *lut_ids, uint32_t B,
-                            const int32_t *luts, int nluts, uint32_t *acc, hipStream_t s)
+                            const int32_t *luts, int nluts, uint32_t *err, uint32_t *acc, hipStream_t s)
 {
     if (!B) return hipSuccess;
-    hipLaunchKernelGGL(k_init_tfhe, dim3((G.N + 255) / 256, B), dim3(256), 0, s, ctN, lut_ids, luts, nluts, acc,
-                       G.n, G.N, G.log2_t);
+    hipLaunchKernelGGL(k_init_tfhe, dim3((G.N + 255) / 256, B), dim3(256), 0, s, ctN, lut_ids, luts, nluts, err,
+                       acc, G.n, G.N, G.log2_t);
     return hipGetLastError();
 }
 
@@ -1609,7 +1715,7 @@ hipError_t launch_keyswitch(const uint32_t *in, uint32_t B, uint32_t din, const 
                             int log2B, int ell, uint32_t out_len, uint32_t *out, hipStream_t s)
 {
     if (!B) return hipSuccess;
-    if (ell > 8) return hipErrorInvalidValue;
+    if (ell > 8 || log2B > 16) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_keyswitch, dim3((out_len + 255) / 256, (B + KS_TB - 1) / KS_TB), dim3(256),
                        0, s, in, B, din, key, log2B, ell, out_len, out);
     return hipGetLastError();
@@ -1649,14 +1755,23 @@ hipError_t launch_affine(const int32_t *W, const uint32_t *in, uint32_t rows, ui
     return hipGetLastError();
 }
 
+hipError_t launch_lincomb2(const uint32_t *x, const uint32_t *y, int32_t wx, int32_t wy, uint32_t count,
+                           uint32_t *out, hipStream_t s)
+{
+    if (!count) return hipSuccess;
+    hipLaunchKernelGGL(k_lincomb2, dim3((count + 255) / 256), dim3(256), 0, s, x, y, (uint32_t)wx, (uint32_t)wy,
+                       count, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_pubmux(const Geometry &G, const uint32_t *rlwe, const uint32_t *ctN,
                          const int32_t *lut_ids, uint32_t E, uint32_t per, const int32_t *luts, int nluts,
-                         uint32_t *acc, hipStream_t s)
+                         uint32_t *err, uint32_t *acc, hipStream_t s)
 {
     if (!E) return hipSuccess;
     if (!per) return hipErrorInvalidValue;
     const size_t lds = ((size_t)(G.boot_ell * 2 * G.N + 15) & ~(size_t)15) + 4 * (size_t)G.N;
-    hipLaunchKernelGGL(k_pubmux, dim3(E), dim3(256), lds, s, rlwe, ctN, lut_ids, luts, nluts, acc,
+    hipLaunchKernelGGL(k_pubmux, dim3(E), dim3(256), lds, s, rlwe, ctN, lut_ids, luts, nluts, err, acc,
                        G.n, G.N, G.log2_t, G.boot_log2B, G.boot_ell, per);
     return hipGetLastError();
 }
@@ -1767,10 +1882,36 @@ static hipError_t br_kara_fit(KaraFit *out)
     });
 }
 
+// The kernel a round of cnt accumulators runs under `form`: the fixed rule
+// for kFormAuto (see launch_br_kara_t), else the form itself where it exists.
+template <int N, int ELL, int CH>
+static uint32_t round_form(uint32_t form, uint32_t cnt, const KaraFit &fit)
+{
+    if constexpr (br_kara_two<N, ELL, CH>()) {
+        if (form == kFormAuto) return cnt > fit.cap1 ? kForm1W2 : (2 * cnt <= fit.cap1 ? kForm2W : kForm1W);
+        return form;
+    } else {
+        return kForm1W;
+    }
+}
+
+// Accumulators per round of a plan: the plan's own round size, else the
+// resident capacity of its form (for kFormAuto the larger capacity).
+static uint32_t plan_round(const BrPlan &plan, const KaraFit &fit)
+{
+    if (plan.round) return plan.round;
+    switch (plan.form) {
+    case kForm1W: return fit.cap1;
+    case kForm1W2: return fit.cap2 ? fit.cap2 : fit.cap1;
+    case kForm2W: return std::max(1u, fit.cap1 / 2);
+    default: return fit.round();
+    }
+}
+
 template <int N, int ELL, int CH>
 static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
                                    uint32_t accs_per_ct, const void *brk_frag, const uint32_t *corr,
-                                   hipStream_t s)
+                                   const BrPlan &plan, hipStream_t s)
 {
     using GK = BrKara<N, ELL, CH>;
     // Launch in rounds of the resident capacity: the workgroups of one launch
@@ -1778,27 +1919,26 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
     // each XCD's L2 once and shared, where a second round started by
     // completions would drift and re-fetch.  A round may begin inside a
     // sample's group of accumulators (a_base), so no round is left short.
+    // The fixed rule (kFormAuto) by round size: more accumulators than one
+    // wavefront per SIMD holds run two wavefronts per SIMD (k_br_kara1w2 with
+    // one wavefront per accumulator); a round that gives every wavefront of
+    // two per accumulator a SIMD runs those; the rest one wavefront per SIMD.
     KaraFit fit;
     hipError_t e0 = br_kara_fit<N, ELL, CH>(&fit);
     if (e0 != hipSuccess) return e0;
-    const uint32_t R = fit.round();
+    const uint32_t R = plan_round(plan, fit);
     for (uint32_t a0 = 0; a0 < A; a0 += R) {
         const uint32_t cnt = std::min(R, A - a0);
-        bool done = false;
+        const uint32_t form = round_form<N, ELL, CH>(plan.form, cnt, fit);
         if constexpr (br_kara_two<N, ELL, CH>()) {
-            if (cnt > fit.cap1) {
-                // more accumulators than one wavefront per SIMD holds: two per SIMD
+            if (form == kForm1W2)
                 hipLaunchKernelGGL((k_br_kara1w2<N, ELL, CH, 1>), dim3(cnt), dim3(64), GK::LDS2W_BYTES, s, acc,
                                    ctN, a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
-                done = true;
-            } else if (2 * cnt <= fit.cap1) {
-                // a small round: two wavefronts per accumulator still give each one a SIMD
+            else if (form == kForm2W)
                 hipLaunchKernelGGL((k_br_kara1w2<N, ELL, CH, 2>), dim3(cnt), dim3(128), GK::LDS2W_BYTES, s, acc,
                                    ctN, a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
-                done = true;
-            }
         }
-        if (!done) {
+        if (form == kForm1W) {
             if constexpr (GK::WPC == 1)
                 hipLaunchKernelGGL((k_br_kara1w<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS_BYTES, s, acc, ctN, a0,
                                    accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
@@ -1807,6 +1947,164 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
                                    ctN, a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
         }
         hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Geometries of the persistent work-queue kernel: narrow (one wavefront per
+// accumulator) and wide (four), and the pairs it is instantiated for.
+#define FDFB_QUEUE_NARROW(X) X(1024, 3, 1) X(256, 2, 2)
+#define FDFB_QUEUE_WIDE(X) X(2048, 2, 2) X(2048, 4, 1)
+
+struct QueueKey {
+    int N, ell, ch;
+    bool operator==(const QueueKey &o) const { return N == o.N && ell == o.ell && ch == o.ch; }
+};
+static QueueKey queue_key(const Geometry &G) { return {G.N, G.g_ell, digit_chunks(G.g_log2B)}; }
+static bool queue_narrow(const QueueKey &k)
+{
+#define X(n_, l_, c_) if (k.N == n_ && k.ell == l_ && k.ch == c_) return true;
+    FDFB_QUEUE_NARROW(X)
+#undef X
+    return false;
+}
+static bool queue_wide(const QueueKey &k)
+{
+#define X(n_, l_, c_) if (k.N == n_ && k.ell == l_ && k.ch == c_) return true;
+    FDFB_QUEUE_WIDE(X)
+#undef X
+    return false;
+}
+
+bool br_queue_supported(const Geometry &G)
+{
+    const QueueKey k = queue_key(G);
+    return queue_narrow(k) || queue_wide(k);
+}
+
+// Resident workgroups of one k_br_queue instantiation on the current device.
+template <int NA, int LA, int CA, int NB, int LB, int CB>
+static hipError_t br_queue_capacity(uint32_t *cap)
+{
+    using Q = BrQueueGeom<NA, LA, CA, NB, LB, CB>;
+    static PerDevice<uint32_t> caps;
+    return caps.get(cap, [](int dev, uint32_t *c) {
+        int cus = 0;
+        hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = kernel_capacity((const void *)k_br_queue<NA, LA, CA, NB, LB, CB>, 256, Q::LDS, cus, c);
+        return e;
+    });
+}
+
+// One launch group: a narrow and a wide geometry and the jobs of either.
+struct QueueGroup {
+    QueueKey narrow{0, 0, 0}, wide{0, 0, 0};
+    std::vector<int> jobs;
+};
+
+static std::vector<QueueGroup> queue_groups(const BrJobDesc *jobs, int njobs)
+{
+    std::vector<QueueKey> nk, wk;
+    for (int j = 0; j < njobs; ++j) {
+        if (!jobs[j].A) continue;
+        const QueueKey k = queue_key(jobs[j].G);
+        auto &v = queue_wide(k) ? wk : nk;
+        if (std::find(v.begin(), v.end(), k) == v.end()) v.push_back(k);
+    }
+    std::vector<QueueGroup> groups;
+    const size_t pairs = std::max(nk.size(), wk.size());
+    for (size_t g = 0; g < pairs; ++g) {
+        // keys pair up in order; a class with fewer keys lends its first key
+        // (whose body then simply gets no items)
+        QueueKey a = g < nk.size() ? nk[g] : QueueKey{1024, 3, 1};
+        QueueKey b = g < wk.size() ? wk[g] : QueueKey{2048, 2, 2};
+        // wide jobs first, so that the longer items start first
+        std::vector<int> mine;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < njobs; ++j) {
+                if (!jobs[j].A) continue;
+                const QueueKey k = queue_key(jobs[j].G);
+                if ((pass == 0 && g < wk.size() && k == b) || (pass == 1 && g < nk.size() && k == a))
+                    mine.push_back(j);
+            }
+        for (size_t lo = 0; lo < mine.size(); lo += kQueueJobs) {
+            QueueGroup qg;
+            qg.narrow = a;
+            qg.wide = b;
+            qg.jobs.assign(mine.begin() + lo, mine.begin() + std::min(mine.size(), lo + kQueueJobs));
+            groups.push_back(qg);
+        }
+    }
+    return groups;
+}
+
+hipError_t br_queue_launches(const BrJobDesc *jobs, int njobs, uint32_t *launches)
+{
+    for (int j = 0; j < njobs; ++j)
+        if (jobs[j].A && !br_queue_supported(jobs[j].G)) return hipErrorInvalidValue;
+    *launches = (uint32_t)queue_groups(jobs, njobs).size();
+    return hipSuccess;
+}
+
+template <int NA, int LA, int CA, int NB, int LB, int CB>
+static hipError_t launch_queue_t(const BrQueue &q, uint32_t *counter, hipStream_t s)
+{
+    using Q = BrQueueGeom<NA, LA, CA, NB, LB, CB>;
+    uint32_t cap = 0;
+    hipError_t e = br_queue_capacity<NA, LA, CA, NB, LB, CB>(&cap);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, counter, 1u, 0u);
+    hipLaunchKernelGGL((k_br_queue<NA, LA, CA, NB, LB, CB>), dim3(std::min(cap, q.items)), dim3(256), Q::LDS, s, q,
+                       counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_br_queue(const BrJobDesc *jobs, int njobs, uint32_t *counters, uint32_t ncounters,
+                           hipStream_t s)
+{
+    for (int j = 0; j < njobs; ++j)
+        if (jobs[j].A && !br_queue_supported(jobs[j].G)) return hipErrorInvalidValue;
+    const std::vector<QueueGroup> groups = queue_groups(jobs, njobs);
+    if (groups.size() > ncounters) return hipErrorInvalidValue;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const QueueGroup &qg = groups[gi];
+        BrQueue q{};
+        uint32_t items = 0;
+        for (int j : qg.jobs) {
+            const BrJobDesc &d = jobs[j];
+            const bool wide = d.G.N > 1024;
+            BrQueueJob &J = q.job[q.njobs++];
+            J.acc = d.acc;
+            J.ctN = d.ctN;
+            J.bfrag = d.bfrag;
+            J.corr = d.corr;
+            J.accs = d.A;
+            J.per = d.per;
+            J.n = (uint32_t)d.G.n;
+            J.log2B = (uint32_t)d.G.g_log2B;
+            J.wide = wide;
+            J.first_item = items;
+            items += wide ? d.A : (d.A + 3) / 4;
+        }
+        q.items = items;
+        if (!items) continue;
+        hipError_t e = hipErrorInvalidValue;
+        bool found = false;
+#define XW(nb_, lb_, cb_)                                                                              \
+    if (!found && qg.wide == QueueKey{nb_, lb_, cb_}) {                                                 \
+        found = true;                                                                                  \
+        e = launch_queue_t<na_, la_, ca_, nb_, lb_, cb_>(q, counters + gi, s);                         \
+    }
+#define XN(n_, l_, c_)                                                                                 \
+    if (!found && qg.narrow == QueueKey{n_, l_, c_}) {                                                  \
+        constexpr int na_ = n_, la_ = l_, ca_ = c_;                                                    \
+        FDFB_QUEUE_WIDE(XW)                                                                            \
+    }
+        FDFB_QUEUE_NARROW(XN)
+#undef XN
+#undef XW
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1833,31 +2131,92 @@ hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN,
     return hipErrorInvalidValue;
 }
 
-hipError_t br_kara_launches(const Geometry &G, uint32_t A, uint32_t accs_per_ct, uint32_t *launches)
+static hipError_t fit_of(const Geometry &G, KaraFit *fit)
+{
+    const int ch = digit_chunks(G.g_log2B);
+#define X(n_, l_, c_) \
+    if (G.N == n_ && G.g_ell == l_ && ch == c_) return br_kara_fit<n_, l_, c_>(fit);
+    FDFB_BR_MFMA_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+bool br_plan_valid(const Geometry &G, const BrPlan &plan)
+{
+    if (!br_mfma_supported(G)) return false;
+    switch (plan.form) {
+    case kFormAuto:
+    case kForm1W: return true;
+    case kForm1W2:
+    case kForm2W: return G.N == 1024 && G.g_ell == 3 && digit_chunks(G.g_log2B) == 1;
+    case kFormQueue: return br_queue_supported(G) && plan.round == 0;
+    default: return false;
+    }
+}
+
+int br_plan_candidates(const Geometry &G, BrPlan *out, int max)
+{
+    const BrPlan all[] = {{kFormAuto, 0}, {kForm1W, 0}, {kForm1W2, 0}, {kForm2W, 0}, {kFormQueue, 0}};
+    int k = 0;
+    KaraFit fit;
+    const bool have_fit = fit_of(G, &fit) == hipSuccess;
+    for (const BrPlan &p : all) {
+        if (!br_plan_valid(G, p)) continue;
+        if (k < max) out[k] = p;
+        ++k;
+        // the same form in rounds of half its capacity (more rounds, fewer
+        // workgroups walking the key together)
+        if (have_fit && (p.form == kForm1W || p.form == kForm1W2)) {
+            const uint32_t half = plan_round(p, fit) / 2;
+            if (half) {
+                if (k < max) out[k] = BrPlan{p.form, half};
+                ++k;
+            }
+        }
+    }
+    return k;
+}
+
+hipError_t br_kara_launches(const Geometry &G, uint32_t A, uint32_t accs_per_ct, const BrPlan &plan,
+                            uint32_t *launches)
 {
     *launches = 0;
     if (!A) return hipSuccess;
+    if (plan.form == kFormQueue) {
+        *launches = 1;
+        return hipSuccess;
+    }
     (void)accs_per_ct;  // a round may split a sample's accumulators
-    const int ch = digit_chunks(G.g_log2B);
-    hipError_t e = hipErrorInvalidValue;
     KaraFit fit;
-#define X(n_, l_, c_) \
-    if (G.N == n_ && G.g_ell == l_ && ch == c_) e = br_kara_fit<n_, l_, c_>(&fit);
-    FDFB_BR_MFMA_CASES(X)
-#undef X
+    hipError_t e = fit_of(G, &fit);
     if (e != hipSuccess) return e;
-    *launches = (A + fit.round() - 1) / fit.round();
+    const uint32_t R = plan_round(plan, fit);
+    *launches = (A + R - 1) / R;
     return hipSuccess;
 }
 
 hipError_t launch_br_kara(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
-                          uint32_t accs_per_ct, const void *brk_frag, const uint32_t *corr, hipStream_t s)
+                          uint32_t accs_per_ct, const void *brk_frag, const uint32_t *corr, const BrPlan &plan,
+                          uint32_t *work, hipStream_t s)
 {
     if (!A) return hipSuccess;
+    if (!br_plan_valid(G, plan)) return hipErrorInvalidValue;
+    if (plan.form == kFormQueue) {
+        if (!work) return hipErrorInvalidValue;
+        BrJobDesc d;
+        d.G = G;
+        d.acc = acc;
+        d.ctN = ctN;
+        d.A = A;
+        d.per = accs_per_ct;
+        d.bfrag = brk_frag;
+        d.corr = corr;
+        return launch_br_queue(&d, 1, work, 1, s);
+    }
     const int ch = digit_chunks(G.g_log2B);
 #define X(n_, l_, c_) \
     if (G.N == n_ && G.g_ell == l_ && ch == c_) \
-        return launch_br_kara_t<n_, l_, c_>(G, acc, ctN, A, accs_per_ct, brk_frag, corr, s);
+        return launch_br_kara_t<n_, l_, c_>(G, acc, ctN, A, accs_per_ct, brk_frag, corr, plan, s);
     FDFB_BR_MFMA_CASES(X)
 #undef X
     return hipErrorInvalidValue;

@@ -28,14 +28,15 @@ def test_bootstrap_batch_graph_replays():
     cts = fd.to_device(ctx.encrypt_debug(msgs, seed=83))
     ids = torch.full((B,), lid, dtype=torch.int32, device="cuda")
     eager = torch.zeros((B, p.n + 1), dtype=torch.int32, device="cuda")
-    ctx.bootstrap_batch(cts, ids, eager)  # warm-up: keys, scratch, kernel attributes
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    # warm-up on the capture stream: keys, this stream's scratch, kernel attributes
+    ctx.bootstrap_batch(cts, ids, eager, stream=s)
     torch.cuda.synchronize()
     want = fd.to_host(eager)
     assert np.array_equal(ctx.decrypt_debug(want)[0], lut[msgs])
 
     out = torch.zeros_like(eager)
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         ctx.bootstrap_batch(cts, ids, out)
@@ -49,3 +50,23 @@ def test_bootstrap_batch_graph_replays():
         torch.cuda.synchronize()
         assert np.array_equal(fd.to_host(out), want), rep
         assert np.array_equal(fd.to_host(other), want), rep
+
+
+def test_capture_without_scratch_is_refused():
+    """A stream with no scratch block yet cannot allocate one under capture:
+    the call fails with a clear error instead of breaking the capture
+    silently (the capture is then invalid and is discarded)."""
+    p = W.C1
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C1"])
+    lid = ctx.register_lut(W.random_lut(81, p.t))
+    ctx.prepare()
+    cts = fd.to_device(ctx.encrypt_debug(W.messages(82, 8, p.t), seed=83))
+    ids = torch.full((8,), lid, dtype=torch.int32, device="cuda")
+    out = torch.zeros((8, p.n + 1), dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(fd.FdfbError) as ei:
+        with torch.cuda.graph(g, stream=s):
+            ctx.bootstrap_batch(cts, ids, out)
+    assert "capture" in str(ei.value)
+    torch.cuda.synchronize()

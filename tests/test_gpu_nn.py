@@ -64,8 +64,10 @@ def test_nn_circuit_784_128_10():
         assert np.array_equal(yo_[r], oracle.keyswitch(y_[r], ok.ksk, p.ks_log2B, p.ks_ell, n + 1))
     r0, r1 = oracle.setup_polynomial(relu, N)
     from concurrent.futures import ThreadPoolExecutor
-    sample = [77]
-    with ThreadPoolExecutor(len(sample)) as ex:
+    # 16 of the 128 bootstraps: both ends and a seeded spread
+    sample = sorted({0, 127} | set(np.random.default_rng(16).choice(np.arange(1, 127), 14, replace=False).tolist()))
+    say(f"nn: oracle on {len(sample)} bootstraps")
+    with ThreadPoolExecutor(16) as ex:
         refs = list(ex.map(lambda k: oracle.fdfb(ok, r0, r1, h_[k], flags=oracle.OUT_EXTRACTED), sample))
     for k, ref in zip(sample, refs):
         assert np.array_equal(hq_[k], ref), k

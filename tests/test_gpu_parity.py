@@ -224,9 +224,55 @@ def test_batch_invariance_and_empty(c1):
         alone = _bootstrap(ctx, cts[k:k + 1], [lid], 0, p.n + 1)
         assert np.array_equal(alone[0], full[k])
     ctx.bootstrap_batch(empty(0, p.n + 1), empty(0), empty(0, p.n + 1))
+    assert ctx.device_errors() == 0
     bad = _bootstrap(ctx, cts[:2], [lid, 999], 0, p.n + 1)
     assert np.array_equal(bad[0], full[0])
-    assert not bad[1].any()  # unknown table: defined all-zero output
+    assert ctx.device_errors() == fd.DEVERR_LUT_ID  # the unknown id is reported ...
+    assert ctx.device_errors() == 0                  # ... once (read clears)
+    # the sample's accumulator is all zero before the function rotation
+    acc = torch.zeros((1, 2 * p.N), dtype=torch.int32, device="cuda")
+    ctx.pubmux(empty(1, p.boot_ell, 2 * p.N).zero_(), empty(1, p.n + 1).zero_(),
+               torch.tensor([-1], dtype=torch.int32, device="cuda"), acc)
+    torch.cuda.synchronize()
+    assert not fd.to_host(acc).any() and ctx.device_errors() == fd.DEVERR_LUT_ID
+
+
+def test_lincomb2(c1):
+    g = np.random.default_rng(12)
+    x, y = u32(g, 13, 65), u32(g, 13, 65)
+    say("lincomb2 13x65")
+    for wx, wy in ((1, -1), (3, 7), (-8, 0), (0x7FFFFFFF, -(1 << 31))):
+        out = fd.to_host(fd.lincomb2(fd.to_device(x), fd.to_device(y), wx, wy, empty(13, 65)))
+        torch.cuda.synchronize()
+        ref = oracle.affine(np.array([[wx, wy]]), np.stack([x.reshape(-1), y.reshape(-1)]))[0].reshape(13, 65)
+        assert np.array_equal(out, ref), (wx, wy)
+
+
+def test_valu_keyswitch_base_above_2_7(oracle_keys_c1):
+    """Key-switching bases above 2^7 take the VALU key switch (the MFMA one
+    needs digits below 2^7): both switches and a full bootstrap against the
+    oracle, bit for bit."""
+    p = W.C1.with_(ks_log2B=8, ks_ell=3, pk_log2B=9, pk_ell=2)
+    seed = W.KEY_SEED["C1"] + 5
+    ctx, ok = fd.Context.keygen(p, seed), oracle.keygen(p, seed)
+    lwe = u32(np.random.default_rng(15), 23, p.N + 1)
+    say("VALU keyswitch / packing keyswitch C1 (2^8 x 3, 2^9 x 2) B=23")
+    d = fd.to_device(lwe)
+    ks = fd.to_host(ctx.keyswitch(d, empty(23, p.n + 1)))
+    pk = fd.to_host(ctx.packing_keyswitch(d, empty(23, 2 * p.N)))
+    torch.cuda.synchronize()
+    for b in range(23):
+        assert np.array_equal(ks[b], oracle.keyswitch(lwe[b], ok.ksk, p.ks_log2B, p.ks_ell, p.n + 1)), b
+        assert np.array_equal(pk[b], oracle.keyswitch(lwe[b], ok.pk, p.pk_log2B, p.pk_ell, 2 * p.N)), b
+    lut = W.random_lut(21, p.t)
+    lid = ctx.register_lut(lut)
+    msgs = np.arange(p.t, dtype=np.uint32)
+    cts = ctx.encrypt_debug(msgs, seed=22)
+    out = _bootstrap(ctx, cts, [lid] * p.t, 0, p.n + 1)
+    r0, r1 = oracle.setup_polynomial(lut, p.N)
+    ref = np.stack(run_oracle_many(lambda k: oracle.fdfb(ok, r0, r1, cts[k]), p.t))
+    assert np.array_equal(out, ref)
+    assert np.array_equal(ctx.decrypt_debug(out)[0], lut[msgs])
 
 
 @pytest.mark.parametrize("form", list(FORMS))
@@ -325,9 +371,9 @@ def test_fdfb_c2_full_batch(c2):
     m, err = ctx.decrypt_debug(out)
     assert np.array_equal(m, lut[msgs])
     r0, r1 = oracle.setup_polynomial(lut, p.N)
-    # 64 samples: both ends, the middle, and a seeded spread over the batch
+    # 128 samples: both ends, the middle, and a seeded spread over the batch
     sample = sorted({0, 1, 511, 512, 1022, 1023} |
-                    set(np.random.default_rng(64).choice(B, 58, replace=False).tolist()))
+                    set(np.random.default_rng(64).choice(np.arange(2, 510), 122, replace=False).tolist()))
     say(f"oracle on {len(sample)} samples")
     refs = run_oracle_many(lambda k: oracle.fdfb(ok, r0, r1, cts[sample[k]]), len(sample))
     for k, idx in enumerate(sample):
@@ -376,9 +422,11 @@ def keys_2048():
     return get
 
 
-@pytest.mark.parametrize("form", ["batched", "direct"])
+@pytest.mark.parametrize("form", ["batched", "direct", "plain"])
 @pytest.mark.parametrize("name", list(N2048))
 def test_blind_rotate_n2048(keys_2048, name, form):
+    if form == "plain" and name == "C4":
+        pytest.skip("the plain kernel's LDS cannot hold C4's key rows (N = 2048, ell = 4)")
     ctx, ok = keys_2048(name)
     p = N2048[name]
     N = p.N
@@ -440,15 +488,16 @@ def test_blind_rotate_rounds_split_samples(keys_2048):
         assert np.array_equal(got[a], refs[k]), a
 
 
-def test_fdfb_n2048_vs_oracle(keys_2048):
+@pytest.mark.parametrize("form", ["batched", "plain"])
+def test_fdfb_n2048_vs_oracle(keys_2048, form):
     ctx, ok = keys_2048("C3B")
     p = W.C3B
     lut = W.random_lut(W.LUT_SEED["C3B"], p.t)
     lid = ctx.register_lut(lut)
     msgs = np.array([0, 1, p.t // 2, p.t - 1, 7, 19, 25, 30], dtype=np.uint32)
     cts = ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C3B"])
-    say("fdfb C3B batched B=8")
-    out = _bootstrap(ctx, cts, [lid] * len(msgs), 0, p.n + 1)
+    say(f"fdfb C3B {form} B=8")
+    out = _bootstrap(ctx, cts, [lid] * len(msgs), FORMS[form], p.n + 1)
     m, _ = ctx.decrypt_debug(out)
     assert np.array_equal(m, lut[msgs])
     r0, r1 = oracle.setup_polynomial(lut, p.N)
