@@ -139,6 +139,33 @@ int fdfb_register_lut(fdfb_ctx *ctx, const uint32_t *table, int32_t *lut_id);
 int fdfb_bootstrap_batch(fdfb_ctx *ctx, const uint32_t *d_cts, const int32_t *d_lut_ids,
                          uint32_t B, uint32_t *d_out, uint32_t flags, void *stream);
 
+/*
+ * Same as fdfb_bootstrap_batch, for callers that cannot allocate memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the scratch lives in one static device buffer of the library
+ * (FDFB_NOALLOC_SCRATCH_BYTES per GPU, held from library load until the
+ * process ends) instead of the context's pool, and the call makes no
+ * allocation of any kind.  Inputs, outputs, flags and results are those of
+ * fdfb_bootstrap_batch, bit for bit.  Limits and errors:
+ *  - the context must already be prepared for these flags (keys, every
+ *    registered table and, with FDFB_DIRECT, the direct key layout resident
+ *    on the device, e.g. by one earlier fdfb_bootstrap_batch or by
+ *    fdfb_prepare): FDFB_EINVAL otherwise;
+ *  - fdfb_noalloc_max_batch gives the largest B whose scratch fits the
+ *    buffer; a larger B is FDFB_EINVAL (nothing is enqueued);
+ *  - every call on a GPU shares that GPU's buffer: calls whose device work
+ *    may overlap (different streams without ordering, or replays of graphs
+ *    that captured this call) race and give undefined results.  Calls in one
+ *    stream's order are safe.  No part of the buffer needs to start at zero.
+ */
+#define FDFB_NOALLOC_SCRATCH_BYTES (64u << 20)
+int fdfb_bootstrap_batch_noalloc(fdfb_ctx *ctx, const uint32_t *d_cts, const int32_t *d_lut_ids,
+                                 uint32_t B, uint32_t *d_out, uint32_t flags, void *stream);
+
+/* Largest B fdfb_bootstrap_batch_noalloc accepts for this context's
+ * parameter set (host only, no device call). */
+int fdfb_noalloc_max_batch(const fdfb_ctx *ctx, uint32_t *max_B);
+
 /* Upload everything a call with these flags needs (keys, registered tables,
  * the direct key layout for FDFB_DIRECT) without enqueuing work, so that
  * later calls only enqueue kernels.  Errors: FDFB_ENOMEM, FDFB_EDEVICE. */

@@ -71,7 +71,7 @@ EXPORTED = [
     "fdfb_br_launches", "fdfb_measure_mfma_peak", "fdfb_set_abort", "fdfb_free", "fdfb_last_error",
     "fdfb_server_create", "fdfb_server_submit", "fdfb_server_poll", "fdfb_server_wait",
     "fdfb_server_stats", "fdfb_server_destroy", "fdfb_affine", "fdfb_lincomb2", "fdfb_prepare",
-    "fdfb_release_scratch", "fdfb_device_errors",
+    "fdfb_release_scratch", "fdfb_device_errors", "fdfb_bootstrap_batch_noalloc", "fdfb_noalloc_max_batch",
     "fdfb_bootstrap_multi_ex", "fdfb_multi_graph_create", "fdfb_graph_launch", "fdfb_graph_info",
     "fdfb_graph_free", "fdfb_br_plans", "fdfb_autotune", "fdfb_br_set_plan", "fdfb_br_get_plan",
     "fdfb_tune_save", "fdfb_tune_load", "fdfb_tune_clear", "fdfb_get_rotation_polys",
@@ -143,6 +143,8 @@ def lib():
             "fdfb_prepare": (i, [P, u32]),
             "fdfb_release_scratch": (i, [P]),
             "fdfb_device_errors": (i, [P, i, P]),
+            "fdfb_bootstrap_batch_noalloc": (i, [P, P, P, u32, P, u32, P]),
+            "fdfb_noalloc_max_batch": (i, [P, P]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -343,6 +345,19 @@ class Context:
         _check(lib().fdfb_bootstrap_batch(self._h, _dev_ptr(cts, "cts"), _dev_ptr(lut_ids, "lut_ids"), B,
                                           _dev_ptr(out, "out"), flags, _stream(stream)))
         return out
+
+    def bootstrap_batch_noalloc(self, cts, lut_ids, out, flags: int = 0, stream=None):
+        """fdfb_bootstrap_batch with its scratch in the library's static buffer
+        (no allocation; the context must be prepared, B <= noalloc_max_batch())."""
+        B = int(cts.shape[0]) if cts.dim() > 1 else 0
+        _check(lib().fdfb_bootstrap_batch_noalloc(self._h, _dev_ptr(cts, "cts"), _dev_ptr(lut_ids, "lut_ids"), B,
+                                                  _dev_ptr(out, "out"), flags, _stream(stream)))
+        return out
+
+    def noalloc_max_batch(self) -> int:
+        n = C.c_uint32()
+        _check(lib().fdfb_noalloc_max_batch(self._h, C.byref(n)))
+        return n.value
 
     def keyswitch(self, d_in, out, stream=None):
         _check(lib().fdfb_keyswitch(self._h, _dev_ptr(d_in, "in"), int(d_in.shape[0]),

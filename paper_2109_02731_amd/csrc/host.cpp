@@ -1435,6 +1435,51 @@ int fdfb_device_errors(fdfb_ctx *c, int clear, uint32_t *bits)
     });
 }
 
+static_assert(FDFB_NOALLOC_SCRATCH_BYTES == fdfbk::kNoallocScratchBytes, "one size for the static scratch");
+
+// Largest batch whose scratch fits the static buffer (scratch_bytes grows with B).
+static uint32_t noalloc_max_batch(const fdfb_params &P)
+{
+    uint32_t lo = 0, hi = 1u << 24;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (scratch_bytes(P, mid, 1) <= FDFB_NOALLOC_SCRATCH_BYTES) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+int fdfb_noalloc_max_batch(const fdfb_ctx *c, uint32_t *max_B)
+{
+    return guarded([&]() -> int {
+        if (!c || !max_B) return fail(FDFB_EINVAL, "null argument");
+        *max_B = noalloc_max_batch(c->P);
+        return FDFB_OK;
+    });
+}
+
+int fdfb_bootstrap_batch_noalloc(fdfb_ctx *c, const uint32_t *d_cts, const int32_t *d_lut_ids, uint32_t B,
+                                 uint32_t *d_out, uint32_t flags, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!c) return fail(FDFB_EINVAL, "null context");
+        if (B == 0) return c->abort_flag.load() ? fail(FDFB_EABORTED, "abort flag raised") : FDFB_OK;
+        Lock lk(c->mu);
+        if (int rc = check_batch(c, d_cts, d_lut_ids, d_out, flags)) return rc;
+        const uint32_t maxB = noalloc_max_batch(c->P);
+        if (B > maxB)
+            return fail(FDFB_EINVAL, "batch of " + std::to_string(B) + " exceeds the static scratch (at most " +
+                                         std::to_string(maxB) + " samples for this parameter set)");
+        if (!device_ready(*c, flags))
+            return fail(FDFB_EINVAL, "context not prepared for these flags: call fdfb_prepare (or one "
+                                     "fdfb_bootstrap_batch) first");
+        void *base = nullptr;
+        K_TRY(fdfbk::noalloc_scratch(&base));
+        const ScratchView sc = carve_scratch(c->P, B, 1, base);
+        return enqueue_bootstrap(*c, sc, d_cts, d_lut_ids, B, d_out, flags, (hipStream_t)stream, 1, false);
+    });
+}
+
 int fdfb_prepare(fdfb_ctx *c, uint32_t flags)
 {
     return guarded([&]() -> int {

@@ -121,4 +121,9 @@ hipError_t launch_pubmux(const Geometry &G, const uint32_t *rlwe, const uint32_t
 hipError_t mfma_stream_capacity(uint32_t *blocks);
 hipError_t launch_mfma_stream(uint32_t blocks, uint32_t iters, int32_t *out, hipStream_t s);
 
+// Static device buffer of the allocation-free bootstrap (bytes per GPU) and
+// its device address on the current device (looked up once per device).
+constexpr size_t kNoallocScratchBytes = 64u << 20;
+hipError_t noalloc_scratch(void **ptr);
+
 }  // namespace fdfbk

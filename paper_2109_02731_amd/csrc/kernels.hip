@@ -2222,4 +2222,26 @@ hipError_t launch_br_kara(const Geometry &G, uint32_t *acc, const uint32_t *ctN,
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free bootstrap: one buffer per GPU, part
+// of the code object, so it exists from library load until the process
+// ends.  Host code must never pass `scratch` itself to a kernel (in host code
+// it names a host-side stand-in); it uses the device address looked up once
+// per device with hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+hipError_t noalloc_scratch(void **ptr)
+{
+    static PerDevice<void *> addr;
+    return addr.get(ptr, [](int, void **out) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        *out = p;
+        return hipSuccess;
+    });
+}
+
 }  // namespace fdfbk
