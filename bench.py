@@ -442,6 +442,10 @@ def main():
                     help="also time the 784->128->10 circuit this many inferences (0 skips)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (the fixed plan rule issues the blind rotations)")
+    ap.add_argument("--plan-sign", default=None, choices=["auto", "1w", "1w2", "2w", "queue"],
+                    help="issue the sign rotations with this plan instead of tuning (for profiles)")
+    ap.add_argument("--plan-func", default=None, choices=["auto", "1w", "1w2", "2w", "queue"],
+                    help="issue the function rotation with this plan instead of tuning (for profiles)")
     ap.add_argument("--batch-sweep", type=int, default=0, metavar="STEPS",
                     help="also time the bench configuration at batch 128..4096 this many steps (0 skips)")
     ap.add_argument("--oracle-timing", action="store_true",
@@ -483,13 +487,19 @@ def main():
         ctx.bootstrap_batch(d_cts, d_ids, d_out, flags=flags)
 
     tuned = None
+    forms = {v: k for k, v in fd.FORMS.items()}
+    if args.plan_sign or args.plan_func:
+        args.no_tune = True
+        if args.plan_sign:
+            ctx.set_plan(B * p.boot_ell, forms[args.plan_sign])
+        if args.plan_func:
+            ctx.set_plan(B, forms[args.plan_func])
     if not args.no_tune:
         # the autotuner times every issue plan of the two rotation phases of
-        # this batch (2048 sign and 1024 function accumulators) and records the
-        # fastest; the timed steps use them
+        # this batch (2048 sign and 1024 function accumulators) inside whole
+        # batches and records the fastest; the timed steps use them
         print("[bench] autotune", file=sys.stderr, flush=True)
-        tuned = {"sign_rotations": ctx.autotune(B * p.boot_ell, p.boot_ell),
-                 "function_rotation": ctx.autotune(B, 1)}
+        tuned = ctx.autotune_bootstrap(B, 1)
     print(f"[bench] keys ready; warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()

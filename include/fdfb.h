@@ -481,6 +481,21 @@ int fdfb_br_plans(fdfb_ctx *ctx, fdfb_br_plan *plans, uint32_t *count);
 int fdfb_autotune(fdfb_ctx *ctx, uint32_t A, uint32_t per, uint32_t reps, fdfb_br_plan *best,
                   fdfb_br_plan *tried, uint32_t *ntried);
 
+/* Tune the two rotation phases of a bootstrap batch where they run: every
+ * plan is timed as part of whole batches of B samples with L tables each
+ * (random samples, table 0, which must be registered), first for the sign
+ * rotations (B ell_boot accumulators) with the function rotation's plan
+ * fixed, then for the function rotation (B L accumulators); each phase's
+ * fastest plan is recorded as fdfb_autotune records it.  Timing a phase
+ * inside the batch catches what isolated timing misses (a launch that
+ * follows other kernels may be placed unevenly on the SIMDs).  sign_best,
+ * func_best: the plans chosen, with the batch time in ms; tried (nullable,
+ * capacity *ntried) every batch timing.  When both phases have the same
+ * accumulator count one plan is searched for both.  Errors: as
+ * fdfb_autotune, FDFB_EINVAL without a registered table. */
+int fdfb_autotune_bootstrap(fdfb_ctx *ctx, uint32_t B, uint32_t L, uint32_t reps, fdfb_br_plan *sign_best,
+                            fdfb_br_plan *func_best, fdfb_br_plan *tried, uint32_t *ntried);
+
 /* Record a plan for A accumulators of the context's geometry (plan = NULL
  * removes the entry, back to the fixed rule), or read the plan in use. */
 int fdfb_br_set_plan(fdfb_ctx *ctx, uint32_t A, const fdfb_br_plan *plan);

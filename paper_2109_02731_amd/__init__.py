@@ -74,7 +74,7 @@ EXPORTED = [
     "fdfb_release_scratch", "fdfb_device_errors", "fdfb_bootstrap_batch_noalloc", "fdfb_noalloc_max_batch",
     "fdfb_bootstrap_multi_ex", "fdfb_multi_graph_create", "fdfb_graph_launch", "fdfb_graph_info",
     "fdfb_graph_free", "fdfb_br_plans", "fdfb_autotune", "fdfb_br_set_plan", "fdfb_br_get_plan",
-    "fdfb_tune_save", "fdfb_tune_load", "fdfb_tune_clear", "fdfb_get_rotation_polys",
+    "fdfb_tune_save", "fdfb_tune_load", "fdfb_tune_clear", "fdfb_get_rotation_polys", "fdfb_autotune_bootstrap",
 ]
 
 FORMS = {0: "auto", 1: "1w", 2: "1w2", 3: "2w", 4: "queue"}
@@ -109,6 +109,7 @@ def lib():
             "fdfb_br_plans": (i, [P, P, P]),
             "fdfb_autotune": (i, [P, u32, u32, u32, P, P, P]),
             "fdfb_br_set_plan": (i, [P, u32, P]),
+            "fdfb_autotune_bootstrap": (i, [P, u32, u32, u32, P, P, P, P]),
             "fdfb_br_get_plan": (i, [P, u32, P]),
             "fdfb_tune_save": (i, [C.c_char_p]),
             "fdfb_tune_load": (i, [C.c_char_p]),
@@ -294,6 +295,17 @@ class Context:
         n = C.c_uint32(cap)
         _check(lib().fdfb_autotune(self._h, A, per, reps, C.byref(best), tried, C.byref(n)))
         return {"best": best.as_dict(), "tried": [tried[k].as_dict() for k in range(min(n.value, cap))]}
+
+    def autotune_bootstrap(self, B: int, L: int = 1, reps: int = 2) -> dict:
+        """Tune both rotation phases of a batch of B samples (L tables each) by
+        timing whole batches; returns the plans chosen and every timing."""
+        sb, fb = _Plan(), _Plan()
+        cap = 32
+        tried = (_Plan * cap)()
+        n = C.c_uint32(cap)
+        _check(lib().fdfb_autotune_bootstrap(self._h, B, L, reps, C.byref(sb), C.byref(fb), tried, C.byref(n)))
+        return {"sign_rotations": sb.as_dict(), "function_rotation": fb.as_dict(),
+                "batch_ms": [tried[k].as_dict() for k in range(min(n.value, cap))]}
 
     def set_plan(self, A: int, form=None, round: int = 0):
         """Force the plan for A accumulators (form None: back to the fixed rule)."""

@@ -284,6 +284,130 @@ int fdfb_autotune(fdfb_ctx *c, uint32_t A, uint32_t per, uint32_t reps, fdfb_br_
     });
 }
 
+int fdfb_autotune_bootstrap(fdfb_ctx *c, uint32_t B, uint32_t L, uint32_t reps, fdfb_br_plan *sign_best,
+                            fdfb_br_plan *func_best, fdfb_br_plan *tried, uint32_t *ntried)
+{
+    return guarded([&]() -> int {
+        if (!c || !sign_best || !func_best || !B || !L || !reps)
+            return fail(FDFB_EINVAL, "null context or result, or B, L, reps = 0");
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (!c->mfma_ok) return fail(FDFB_ENOTSUP, "no batched blind rotation for this parameter set");
+        if (c->nluts < 1) return fail(FDFB_EINVAL, "register a table first (the timing batch uses table 0)");
+        if ((uint64_t)B * L > 0xFFFFFFFFu) return fail(FDFB_EINVAL, "too many table evaluations");
+        if (int rc = fdfbi::ensure_device(*c)) return rc;
+        const fdfbk::Geometry &G = c->geom;
+        const uint32_t As = B * (uint32_t)G.boot_ell, Af = B * L;
+        fdfbk::BrPlan cand[16];
+        const int nc = std::min(fdfbk::br_plan_candidates(G, cand, 16), 16);
+        // a timing batch: random samples (their outputs are never read), table 0
+        const size_t in_words = (size_t)B * (G.n + 1), out_words = (size_t)Af * (G.n + 1);
+        const size_t sbytes = fdfbi::scratch_bytes(c->P, B, L);
+        uint32_t *d_cts = nullptr, *d_out = nullptr;
+        int32_t *d_ids = nullptr;
+        void *d_scr = nullptr;
+        hipStream_t st = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const uint32_t cus = device_cus();
+        // the table entries this search may overwrite, restored on failure
+        std::vector<Entry> saved;
+        {
+            std::lock_guard<std::mutex> tl(g_mu);
+            ensure_loaded_locked();
+            saved = g_table;
+        }
+        auto done = [&](int rc) {
+            if (st) (void)hipStreamSynchronize(st);
+            for (void *p : {(void *)d_cts, (void *)d_out, (void *)d_ids, d_scr})
+                if (p) (void)hipFree(p);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (st) (void)hipStreamDestroy(st);
+            if (rc) {
+                std::lock_guard<std::mutex> tl(g_mu);
+                g_table = saved;
+            }
+            return rc;
+        };
+        hipError_t e = hipMalloc((void **)&d_cts, in_words * 4);
+        if (e == hipSuccess) e = hipMalloc((void **)&d_out, out_words * 4);
+        if (e == hipSuccess) e = hipMalloc((void **)&d_ids, (size_t)Af * 4);
+        if (e == hipSuccess) e = hipMalloc(&d_scr, sbytes);
+        if (e == hipSuccess) {
+            std::vector<uint32_t> h(in_words);
+            for (size_t k = 0; k < in_words; ++k) h[k] = (uint32_t)mix(k + (3ull << 40));
+            e = hipMemcpy(d_cts, h.data(), in_words * 4, hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess) e = hipMemset(d_ids, 0, (size_t)Af * 4);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e != hipSuccess) return done(fail(FDFB_EDEVICE, std::string("autotune buffers: ") + hipGetErrorString(e)));
+        const fdfbi::ScratchView sc = fdfbi::carve_scratch(c->P, B, L, d_scr);
+        auto set = [&](uint32_t A, const fdfbk::BrPlan &p, double ms) {
+            std::lock_guard<std::mutex> tl(g_mu);
+            put(Entry{cus, (uint32_t)G.N, (uint32_t)G.g_ell, (uint32_t)fdfbk::digit_chunks(G.g_log2B), (uint32_t)G.n,
+                      A, p, ms});
+        };
+        // milliseconds per bootstrap batch with the current table
+        auto time_batch = [&](double *ms) -> int {
+            int rc = fdfbi::enqueue_bootstrap(*c, sc, d_cts, d_ids, B, d_out, 0, st, L, false);  // warm-up
+            if (rc) return rc;
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) return fail(FDFB_EDEVICE, hipGetErrorString(e));
+            for (uint32_t r = 0; r < reps; ++r)
+                if ((rc = fdfbi::enqueue_bootstrap(*c, sc, d_cts, d_ids, B, d_out, 0, st, L, false))) return rc;
+            if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+                return fail(FDFB_EDEVICE, hipGetErrorString(e));
+            float t = 0.f;
+            if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return fail(FDFB_EDEVICE, hipGetErrorString(e));
+            *ms = (double)t / reps;
+            return FDFB_OK;
+        };
+        {  // both phases start from the fixed rule
+            std::lock_guard<std::mutex> tl(g_mu);
+            g_table.erase(std::remove_if(g_table.begin(), g_table.end(),
+                                         [&](const Entry &x) {
+                                             return same_key(x, cus, G, As) || same_key(x, cus, G, Af);
+                                         }),
+                          g_table.end());
+        }
+        std::vector<fdfb_br_plan> all;
+        // one phase at a time (the other keeps its current plan); with As == Af
+        // one plan serves both phases and they are searched together
+        const uint32_t phases[2] = {As, Af};
+        fdfb_br_plan best[2] = {};
+        for (int ph = 0; ph < (As == Af ? 1 : 2); ++ph) {
+            int bi = -1;
+            double bms = 0.0;
+            for (int k = 0; k < nc; ++k) {
+                set(phases[ph], cand[k], 0.0);
+                double ms = 0.0;
+                if (int rc = time_batch(&ms)) return done(rc);
+                all.push_back(fdfb_br_plan{cand[k].form, cand[k].round, ms});
+                if (bi < 0 || ms < bms) {
+                    bi = k;
+                    bms = ms;
+                }
+            }
+            set(phases[ph], cand[bi], bms);
+            best[ph] = fdfb_br_plan{cand[bi].form, cand[bi].round, bms};
+        }
+        if (As == Af) best[1] = best[0];
+        *sign_best = best[0];
+        *func_best = best[1];
+        if (ntried) {
+            if (tried)
+                for (size_t k = 0; k < all.size() && k < *ntried; ++k) tried[k] = all[k];
+            *ntried = (uint32_t)all.size();
+        }
+        if (const char *path = std::getenv("FDFB_TUNE_CACHE"))
+            if (*path) {
+                std::lock_guard<std::mutex> tl(g_mu);
+                if (int rc = save_locked(path)) return done(rc);
+            }
+        return done(FDFB_OK);
+    });
+}
+
 int fdfb_tune_save(const char *path)
 {
     return guarded([&]() -> int {

@@ -74,10 +74,23 @@ def test_autotune_records_and_caches(tmp_path, monkeypatch):
     assert ctx.get_plan(2048)["form"] == res_s["best"]["form"]
     entries = json.loads(path.read_text())
     assert {e["A"] for e in entries} == {1024, 2048}
+    # tuning inside whole batches (needs a table), then the cache again
+    lid0 = ctx.register_lut(W.random_lut(7, p.t))
+    assert lid0 == 0
+    say("autotune C2 bootstrap batch of 1024")
+    res_b = ctx.autotune_bootstrap(1024, 1)
+    n_plans = len(ctx.br_plans())
+    assert len(res_b["batch_ms"]) == 2 * n_plans
+    assert res_b["sign_rotations"]["ms"] == min(t["ms"] for t in res_b["batch_ms"][:n_plans])
+    assert ctx.get_plan(2048)["form"] == res_b["sign_rotations"]["form"]
+    assert ctx.get_plan(1024)["form"] == res_b["function_rotation"]["form"]
+    entries = json.loads(path.read_text())
+    assert {e["A"] for e in entries} == {1024, 2048}
     # a bootstrap with the tuned plans: same bits as with the fixed rule
     lut = W.random_lut(W.LUT_SEED["C2"], p.t)
     lid = ctx.register_lut(lut)
     B = 1024
+    res_s = {"best": ctx.get_plan(2048)}
     msgs = W.messages(W.MSG_SEED["C2"], B, p.t)
     cts = fd.to_device(ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C2"]))
     ids = torch.full((B,), lid, dtype=torch.int32, device="cuda")
