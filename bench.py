@@ -251,6 +251,36 @@ def mixed_bench(fd, torch, W, ctx2, steps: int):
             "correct": bool(ok), "steps": steps}
 
 
+def pipeline_bench(fd, torch, ctx, d_cts, d_ids, ref, batches: int, single_ms: float):
+    """A stream of `batches` batches of the bench workload bootstrapped as a
+    software pipeline (fdfb_bootstrap_pipeline): batch k's function rotation
+    shares persistent work-queue launches with the sign rotations of the
+    batches after it, at 1, 2, 4 and 8 rounds of the resident capacity per
+    launch.  Every batch's output is checked bit for bit against the
+    separate call's."""
+    B = int(d_cts.shape[0])
+    outs = [torch.empty_like(ref) for _ in range(batches)]
+    jobs = [(ctx, d_cts, d_ids, o, 0) for o in outs]
+    by_rounds, ok = {}, True
+    for rounds in (1, 2, 4, 8):
+        fd.bootstrap_pipeline(jobs, rounds=rounds)
+        torch.cuda.synchronize()
+        ok = ok and all(torch.equal(o, ref) for o in outs)
+        t0 = time.perf_counter()
+        for _ in range(2):
+            fd.bootstrap_pipeline(jobs, rounds=rounds)
+        torch.cuda.synchronize()
+        by_rounds[rounds] = (time.perf_counter() - t0) / 2 / batches * 1e3
+    best = min(by_rounds, key=by_rounds.get)
+    ms = by_rounds[best]
+    return {"bootstraps_per_s": B / (ms * 1e-3), "ms_per_batch": ms, "rounds_per_launch": best,
+            "ms_per_batch_by_rounds": {str(k): v for k, v in by_rounds.items()}, "batches": batches,
+            "vs_separate_calls": single_ms / ms, "bit_identical_to_separate_calls": bool(ok),
+            "what": f"{batches} batches of {B} as one software-pipelined submission: each persistent work-queue "
+                    "launch holds whole rounds of two wavefronts per SIMD, batch k's function rotation beside "
+                    "the next batches' sign rotations"}
+
+
 def nn_bench(fd, torch, W, steps: int):
     """Config 4, the NN-shaped circuit: x in Z_32^784 -> dense 784->128 on LWE
     samples -> FDFB ReLU on the 128 outputs (extracted) -> dense 128->10 ->
@@ -438,6 +468,8 @@ def main():
                     help="also time every parameter preset at batch 1024 this many steps (0 skips)")
     ap.add_argument("--mixed-steps", type=int, default=2,
                     help="also time the uneven two-degree batch (one multi-job submission) this many times (0 skips)")
+    ap.add_argument("--pipeline-batches", type=int, default=16,
+                    help="also time a stream of this many bench batches as one software pipeline (0 skips)")
     ap.add_argument("--nn-steps", type=int, default=3,
                     help="also time the 784->128->10 circuit this many inferences (0 skips)")
     ap.add_argument("--no-tune", action="store_true",
@@ -643,6 +675,11 @@ def main():
         print("[bench] NN-shaped circuit", file=sys.stderr, flush=True)
         nn = nn_bench(fd, torch, W, args.nn_steps)
 
+    pipe = None
+    if args.pipeline_batches > 0:
+        print(f"[bench] software pipeline of {args.pipeline_batches} batches", file=sys.stderr, flush=True)
+        pipe = pipeline_bench(fd, torch, ctx, d_cts, d_ids, d_out, args.pipeline_batches, wall / K * 1e3)
+
     mixed = None
     if args.mixed_steps > 0:
         print("[bench] uneven two-degree batch", file=sys.stderr, flush=True)
@@ -700,6 +737,7 @@ def main():
         "signed_boot_digit": signed,
         "tfhe_yardstick": tfhe,
         "direct_form": direct,
+        "pipeline": pipe,
         "mixed": mixed,
         "nn_circuit": nn,
         "tuned": tuned,

@@ -238,6 +238,25 @@ int fdfb_bootstrap_multi(const fdfb_job *jobs, uint32_t njobs, void *stream);
 int fdfb_bootstrap_multi_ex(const fdfb_job *jobs, uint32_t njobs, int use_queue, void *stream);
 
 /*
+ * Bootstrap a sequence of jobs (batches) as a software pipeline on one
+ * stream: job k's function rotation shares persistent work-queue launches
+ * with the sign rotations of the jobs after it, so that every launch holds
+ * whole rounds of the kernel's resident capacity (two wavefronts per SIMD)
+ * although one batch's function rotation alone fills only half of it.  Each
+ * launch takes the function rotations of the jobs whose public mux is
+ * enqueued, then the next jobs' sign rotations in job order (a job's may be
+ * split between launches at whole samples) up to `rounds` rounds of the
+ * resident capacity (0: 4; at most 64); the jobs' outputs follow the launch
+ * that rotates them, in job order.  The steps of each job are those of
+ * Fig. 2 (Sec. 3.2) and its outputs are bit-identical to
+ * fdfb_bootstrap_batch on the job.  Every job's blind rotations must be in
+ * the default form and of a geometry the persistent kernel takes (see
+ * fdfb_bootstrap_multi): FDFB_EINVAL otherwise, before anything is enqueued.
+ * Scratch, limits and other errors as fdfb_bootstrap_multi.
+ */
+int fdfb_bootstrap_pipeline(const fdfb_job *jobs, uint32_t njobs, uint32_t rounds, void *stream);
+
+/*
  * A multi-job submission captured once into a HIP graph and replayed with one
  * launch (hipGraphLaunch): the whole bootstrap of every job, with the
  * persistent work-queue rotations (use_queue as in fdfb_bootstrap_multi_ex).

@@ -75,6 +75,7 @@ EXPORTED = [
     "fdfb_bootstrap_multi_ex", "fdfb_multi_graph_create", "fdfb_graph_launch", "fdfb_graph_info",
     "fdfb_graph_free", "fdfb_br_plans", "fdfb_autotune", "fdfb_br_set_plan", "fdfb_br_get_plan",
     "fdfb_tune_save", "fdfb_tune_load", "fdfb_tune_clear", "fdfb_get_rotation_polys", "fdfb_autotune_bootstrap",
+    "fdfb_bootstrap_pipeline",
 ]
 
 FORMS = {0: "auto", 1: "1w", 2: "1w2", 3: "2w", 4: "queue"}
@@ -102,6 +103,7 @@ def lib():
             "fdfb_tfhe_bootstrap_batch": (i, [P, P, P, u32, P, u32, P]),
             "fdfb_bootstrap_multi": (i, [P, u32, P]),
             "fdfb_bootstrap_multi_ex": (i, [P, u32, i, P]),
+            "fdfb_bootstrap_pipeline": (i, [P, u32, u32, P]),
             "fdfb_multi_graph_create": (i, [P, u32, i, P]),
             "fdfb_graph_launch": (i, [P, P]),
             "fdfb_graph_info": (i, [P, P, C.POINTER(sz)]),
@@ -485,6 +487,14 @@ def bootstrap_multi(jobs, stream=None, use_queue=None):
         _check(lib().fdfb_bootstrap_multi(arr, len(jobs), _stream(stream)))
     else:
         _check(lib().fdfb_bootstrap_multi_ex(arr, len(jobs), 1 if use_queue else 0, _stream(stream)))
+
+
+def bootstrap_pipeline(jobs, rounds=0, stream=None):
+    """jobs: list of (Context, cts, lut_ids, out, flags), bootstrapped as a
+    software pipeline (fdfb_bootstrap_pipeline): job k's function rotation
+    shares persistent launches with the next jobs' sign rotations.  rounds:
+    resident-capacity rounds per launch (0: the library's default)."""
+    _check(lib().fdfb_bootstrap_pipeline(_jobs(jobs), len(jobs), int(rounds), _stream(stream)))
 
 
 class MultiGraph:

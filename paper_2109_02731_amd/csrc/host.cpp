@@ -8,6 +8,7 @@
 #include <climits>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -683,6 +684,53 @@ bool queue_eligible(const fdfb_ctx &c, uint32_t flags)
     return !(flags & (FDFB_PLAIN | FDFB_DIRECT)) && c.mfma_ok && fdfbk::br_queue_supported(c.geom);
 }
 
+// The steps of one job before, between and after its blind rotations.
+static int job_front(const fdfb_job &j, const ScratchView &sc, hipStream_t st)
+{
+    K_TRY(fdfbk::launch_modswitch(j.ctx->geom, j.d_cts, j.B, sc.ctN, st));
+    K_TRY(fdfbk::launch_init_sign(j.ctx->geom, sc.ctN, j.B, sc.acc_sign, st));
+    return FDFB_OK;
+}
+
+static int job_mid(const fdfb_job &j, const ScratchView &sc, hipStream_t st)
+{
+    fdfb_ctx &c = *j.ctx;
+    const fdfbk::Geometry &G = c.geom;
+    K_TRY(fdfbk::launch_extract(G, sc.acc_sign, j.B * G.boot_ell, G.boot_ell, 1u << (31 - G.log2_t), sc.cbits, st));
+    K_TRY(run_ks(c, true, sc.cbits, j.B * G.boot_ell, sc.rbits, st));
+    K_TRY(fdfbk::launch_pubmux(G, sc.rbits, sc.ctN, j.d_lut_ids, j.B, 1, c.d_luts, c.nluts, c.d_err, sc.accf, st));
+    return FDFB_OK;
+}
+
+static int job_back(const fdfb_job &j, const ScratchView &sc, hipStream_t st)
+{
+    fdfb_ctx &c = *j.ctx;
+    if (j.flags & FDFB_OUT_EXTRACTED) {
+        K_TRY(fdfbk::launch_extract(c.geom, sc.accf, j.B, 1, 0, j.d_out, st));
+    } else {
+        K_TRY(fdfbk::launch_extract(c.geom, sc.accf, j.B, 1, 0, sc.cq, st));
+        K_TRY(run_ks(c, false, sc.cq, j.B, j.d_out, st));
+    }
+    return FDFB_OK;
+}
+
+// Queue descriptor of accumulators [a0, a0 + A) of job j's sign rotations
+// (a0 a multiple of the accumulators per sample) or of its function rotation.
+static fdfbk::BrJobDesc job_desc(const fdfb_job &j, const ScratchView &sc, bool sign, uint32_t a0, uint32_t A)
+{
+    const fdfb_ctx &c = *j.ctx;
+    const uint32_t per = sign ? c.geom.boot_ell : 1, N = c.P.N;
+    fdfbk::BrJobDesc x;
+    x.G = c.geom;
+    x.acc = (sign ? sc.acc_sign : sc.accf) + (size_t)a0 * 2 * N;
+    x.ctN = sc.ctN + (size_t)(a0 / per) * (c.P.n + 1);
+    x.A = A;
+    x.per = per;
+    x.bfrag = c.d_brk_frag;
+    x.corr = c.d_brk_corr;
+    return x;
+}
+
 int enqueue_multi(const fdfb_job *jobs, uint32_t njobs, const ScratchView *views, uint32_t *counters,
                   uint32_t ncounters, bool use_queue, hipStream_t st)
 {
@@ -693,32 +741,18 @@ int enqueue_multi(const fdfb_job *jobs, uint32_t njobs, const ScratchView *views
         for (uint32_t k = 0; k < njobs; ++k) {
             const fdfb_job &j = jobs[k];
             if (!j.B) continue;
-            const fdfb_ctx &c = *j.ctx;
-            const uint32_t eb = c.geom.boot_ell;
-            if (use_queue && queue_eligible(c, j.flags)) {
-                fdfbk::BrJobDesc x;
-                x.G = c.geom;
-                x.acc = sign ? views[k].acc_sign : views[k].accf;
-                x.ctN = views[k].ctN;
-                x.A = sign ? j.B * eb : j.B;
-                x.per = sign ? eb : 1;
-                x.bfrag = c.d_brk_frag;
-                x.corr = c.d_brk_corr;
-                d.push_back(x);
-            } else {
+            if (use_queue && queue_eligible(*j.ctx, j.flags))
+                d.push_back(job_desc(j, views[k], sign, 0, sign ? j.B * j.ctx->geom.boot_ell : j.B));
+            else
                 others.push_back(k);
-            }
         }
     };
     std::vector<fdfbk::BrJobDesc> d;
     std::vector<uint32_t> others;
     // ModSwitch and sign accumulators of every job
-    for (uint32_t k = 0; k < njobs; ++k) {
-        const fdfb_job &j = jobs[k];
-        if (!j.B) continue;
-        K_TRY(fdfbk::launch_modswitch(j.ctx->geom, j.d_cts, j.B, views[k].ctN, st));
-        K_TRY(fdfbk::launch_init_sign(j.ctx->geom, views[k].ctN, j.B, views[k].acc_sign, st));
-    }
+    for (uint32_t k = 0; k < njobs; ++k)
+        if (jobs[k].B)
+            if (int rc = job_front(jobs[k], views[k], st)) return rc;
     // the sign rotations of all jobs
     descs(true, d, others);
     uint32_t launches = 0;
@@ -731,18 +765,9 @@ int enqueue_multi(const fdfb_job *jobs, uint32_t njobs, const ScratchView *views
                      j.flags, views[k].work, st));
     }
     // bit samples, packing key switch, public mux of every job
-    for (uint32_t k = 0; k < njobs; ++k) {
-        const fdfb_job &j = jobs[k];
-        if (!j.B) continue;
-        fdfb_ctx &c = *j.ctx;
-        const fdfbk::Geometry &G = c.geom;
-        const ScratchView &sc = views[k];
-        K_TRY(fdfbk::launch_extract(G, sc.acc_sign, j.B * G.boot_ell, G.boot_ell, 1u << (31 - G.log2_t), sc.cbits,
-                                    st));
-        K_TRY(run_ks(c, true, sc.cbits, j.B * G.boot_ell, sc.rbits, st));
-        K_TRY(fdfbk::launch_pubmux(G, sc.rbits, sc.ctN, j.d_lut_ids, j.B, 1, c.d_luts, c.nluts, c.d_err, sc.accf,
-                                   st));
-    }
+    for (uint32_t k = 0; k < njobs; ++k)
+        if (jobs[k].B)
+            if (int rc = job_mid(jobs[k], views[k], st)) return rc;
     // the function rotations of all jobs
     descs(false, d, others);
     K_TRY(fdfbk::launch_br_queue(d.data(), (int)d.size(), counters + launches, ncounters - launches, st));
@@ -751,16 +776,77 @@ int enqueue_multi(const fdfb_job *jobs, uint32_t njobs, const ScratchView *views
         K_TRY(run_br(*j.ctx, views[k].accf, views[k].ctN, j.B, 1, j.flags, views[k].work, st));
     }
     // SampleExtract and the final key switch of every job
-    for (uint32_t k = 0; k < njobs; ++k) {
-        const fdfb_job &j = jobs[k];
-        if (!j.B) continue;
-        fdfb_ctx &c = *j.ctx;
-        const ScratchView &sc = views[k];
-        if (j.flags & FDFB_OUT_EXTRACTED) {
-            K_TRY(fdfbk::launch_extract(c.geom, sc.accf, j.B, 1, 0, j.d_out, st));
-        } else {
-            K_TRY(fdfbk::launch_extract(c.geom, sc.accf, j.B, 1, 0, sc.cq, st));
-            K_TRY(run_ks(c, false, sc.cq, j.B, j.d_out, st));
+    for (uint32_t k = 0; k < njobs; ++k)
+        if (jobs[k].B)
+            if (int rc = job_back(jobs[k], views[k], st)) return rc;
+    return FDFB_OK;
+}
+
+int enqueue_pipeline(const fdfb_job *jobs, uint32_t njobs, const ScratchView *views, uint32_t *counters,
+                     uint32_t ncounters, uint32_t rounds, hipStream_t st)
+{
+    // resident workgroups of the persistent kernel for these jobs
+    std::vector<fdfbk::BrJobDesc> all;
+    for (uint32_t k = 0; k < njobs; ++k)
+        if (jobs[k].B) all.push_back(job_desc(jobs[k], views[k], false, 0, jobs[k].B));
+    uint32_t cap = 0;
+    K_TRY(fdfbk::br_queue_slots(all.data(), (int)all.size(), &cap));
+    if (!cap) return FDFB_OK;
+    const uint64_t target = (uint64_t)rounds * cap;
+
+    std::vector<uint32_t> s_next(njobs, 0);  // sign accumulators of each job scheduled so far
+    std::vector<uint32_t> ready;             // jobs whose public mux is enqueued
+    uint32_t ks = 0;                         // first job with sign accumulators left to schedule
+    std::vector<fdfbk::BrJobDesc> d;
+    std::vector<uint32_t> f_jobs, s_done;
+    for (;;) {
+        d.clear();
+        f_jobs.clear();
+        s_done.clear();
+        uint64_t items = 0;
+        // function rotations whose inputs are enqueued
+        for (uint32_t k : ready) {
+            d.push_back(job_desc(jobs[k], views[k], false, 0, jobs[k].B));
+            items += fdfbk::br_queue_items(jobs[k].ctx->geom, jobs[k].B);
+            f_jobs.push_back(k);
+        }
+        ready.clear();
+        // then sign rotations of the next jobs, up to whole rounds of the resident capacity
+        const uint64_t goal = std::max(target, (items + cap - 1) / cap * cap);
+        while (ks < njobs && items < goal) {
+            const fdfb_job &j = jobs[ks];
+            if (!j.B) {
+                ++ks;
+                continue;
+            }
+            const fdfbk::Geometry &G = j.ctx->geom;
+            const uint32_t per = G.boot_ell, total = j.B * per;
+            if (s_next[ks] == 0)
+                if (int rc = job_front(j, views[ks], st)) return rc;
+            // cut points: whole samples, and whole items of a narrow geometry
+            const uint32_t gran = G.N > 1024 ? per : std::lcm(4u, per);
+            const uint64_t room = G.N > 1024 ? goal - items : (goal - items) * 4;
+            uint32_t take = total - s_next[ks];
+            if (take > room) take = (uint32_t)(room / gran * gran);
+            if (!take) break;
+            d.push_back(job_desc(j, views[ks], true, s_next[ks], take));
+            items += fdfbk::br_queue_items(G, take);
+            s_next[ks] += take;
+            if (s_next[ks] == total) {
+                s_done.push_back(ks);
+                ++ks;
+            }
+        }
+        if (d.empty()) break;
+        uint32_t launches = 0;
+        K_TRY(fdfbk::br_queue_launches(d.data(), (int)d.size(), &launches));
+        if (launches > ncounters) return fail(FDFB_EINVAL, "too many job groups for one launch");
+        K_TRY(fdfbk::launch_br_queue(d.data(), (int)d.size(), counters, ncounters, st));
+        for (uint32_t k : f_jobs)
+            if (int rc = job_back(jobs[k], views[k], st)) return rc;
+        for (uint32_t k : s_done) {
+            if (int rc = job_mid(jobs[k], views[k], st)) return rc;
+            ready.push_back(k);
         }
     }
     return FDFB_OK;
@@ -1006,6 +1092,28 @@ int fdfb_bootstrap_multi_ex(const fdfb_job *jobs, uint32_t njobs, int use_queue,
         if (!counters) return FDFB_OK;  // no samples
         const bool queue = use_queue < 0 ? multi_uses_queue(jobs, njobs) : use_queue == 1;
         return enqueue_multi(jobs, njobs, views.data(), counters, kWorkWords, queue, (hipStream_t)stream);
+    });
+}
+
+int fdfb_bootstrap_pipeline(const fdfb_job *jobs, uint32_t njobs, uint32_t rounds, void *stream)
+{
+    return guarded([&]() -> int {
+        if (rounds > kMaxPipelineRounds)
+            return fail(FDFB_EINVAL, "rounds must be at most " + std::to_string(kMaxPipelineRounds));
+        std::vector<std::unique_lock<std::recursive_mutex>> locks;
+        if (int rc = lock_jobs(jobs, njobs, locks)) return rc;
+        if (njobs > kMaxJobs) return fail(FDFB_EINVAL, "at most " + std::to_string(kMaxJobs) + " jobs per submission");
+        for (uint32_t k = 0; k < njobs; ++k)
+            if (jobs[k].B && !queue_eligible(*jobs[k].ctx, jobs[k].flags))
+                return fail(FDFB_EINVAL, "job " + std::to_string(k) +
+                                             ": its blind rotations are not in a form the work-queue kernel takes");
+        if (int rc = check_jobs(jobs, njobs)) return rc;
+        std::vector<ScratchView> views;
+        uint32_t *counters = nullptr;
+        if (int rc = multi_scratch(jobs, njobs, stream, views, &counters)) return rc;
+        if (!counters) return FDFB_OK;  // no samples
+        return enqueue_pipeline(jobs, njobs, views.data(), counters, kWorkWords, rounds ? rounds : 4,
+                                (hipStream_t)stream);
     });
 }
 

@@ -143,5 +143,14 @@ bool queue_eligible(const fdfb_ctx &c, uint32_t flags);
 // device words for the queue launches.
 int enqueue_multi(const fdfb_job *jobs, uint32_t njobs, const ScratchView *views, uint32_t *counters,
                   uint32_t ncounters, bool use_queue, hipStream_t st);
+// Enqueue queue-eligible jobs as a software pipeline: each persistent
+// work-queue launch takes the function rotations of the jobs whose public
+// mux is enqueued, then the next jobs' sign rotations (split at whole samples)
+// up to `rounds` rounds of the kernel's resident capacity; after it, the
+// outputs of those function rotations and the public mux of every job whose
+// sign rotations are complete.  The counters are reused by every launch.
+int enqueue_pipeline(const fdfb_job *jobs, uint32_t njobs, const ScratchView *views, uint32_t *counters,
+                     uint32_t ncounters, uint32_t rounds, hipStream_t st);
+constexpr uint32_t kMaxPipelineRounds = 64;
 
 }  // namespace fdfbi

@@ -2110,6 +2110,37 @@ hipError_t launch_br_queue(const BrJobDesc *jobs, int njobs, uint32_t *counters,
     return hipSuccess;
 }
 
+uint32_t br_queue_items(const Geometry &G, uint32_t accs) { return G.N > 1024 ? accs : (accs + 3) / 4; }
+
+hipError_t br_queue_slots(const BrJobDesc *jobs, int njobs, uint32_t *items)
+{
+    for (int j = 0; j < njobs; ++j)
+        if (jobs[j].A && !br_queue_supported(jobs[j].G)) return hipErrorInvalidValue;
+    uint32_t best = 0;
+    for (const QueueGroup &qg : queue_groups(jobs, njobs)) {
+        uint32_t cap = 0;
+        hipError_t e = hipErrorInvalidValue;
+        bool found = false;
+#define XW(nb_, lb_, cb_)                                                                              \
+    if (!found && qg.wide == QueueKey{nb_, lb_, cb_}) {                                                 \
+        found = true;                                                                                  \
+        e = br_queue_capacity<na_, la_, ca_, nb_, lb_, cb_>(&cap);                                     \
+    }
+#define XN(n_, l_, c_)                                                                                 \
+    if (!found && qg.narrow == QueueKey{n_, l_, c_}) {                                                  \
+        constexpr int na_ = n_, la_ = l_, ca_ = c_;                                                    \
+        FDFB_QUEUE_WIDE(XW)                                                                            \
+    }
+        FDFB_QUEUE_NARROW(XN)
+#undef XN
+#undef XW
+        if (e != hipSuccess) return e;
+        best = best ? std::min(best, cap) : cap;
+    }
+    *items = best;
+    return hipSuccess;
+}
+
 bool br_mfma_supported(const Geometry &G)
 {
     const int ch = digit_chunks(G.g_log2B);

@@ -188,6 +188,13 @@ def test_every_entry_point_survives_null_and_zero_arguments():
     assert L.fdfb_prepare(ctx._h, fd.PLAIN | fd.DIRECT) == -1
     job = fd._Job(None, None, None, 1, None, 0)
     assert L.fdfb_bootstrap_multi(C.byref(job), 1, nul) == -1
+    assert L.fdfb_bootstrap_pipeline(C.byref(job), 1, 0, nul) == -1
+    assert L.fdfb_bootstrap_pipeline(nul, 1, 0, nul) == -1
+    # the pipeline takes only rotations the work-queue kernel runs, and at most 64 rounds per launch
+    plain = fd._Job(ctx._h, 16, 16, 1, 16, fd.PLAIN)
+    assert L.fdfb_bootstrap_pipeline(C.byref(plain), 1, 0, nul) == -1
+    assert "work-queue" in fd.lib().fdfb_last_error().decode()
+    assert L.fdfb_bootstrap_pipeline(C.byref(job), 1, 65, nul) == -1
 
 
 def test_context_lock_serialises_threads():
