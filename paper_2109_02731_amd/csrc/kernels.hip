@@ -2110,6 +2110,15 @@ hipError_t launch_br_queue(const BrJobDesc *jobs, int njobs, uint32_t *counters,
     return hipSuccess;
 }
 
+bool br_mfma_supported(const Geometry &G)
+{
+    const int ch = digit_chunks(G.g_log2B);
+#define X(n_, l_, c_) if (G.N == n_ && G.g_ell == l_ && ch == c_) return true;
+    FDFB_BR_MFMA_CASES(X)
+#undef X
+    return false;
+}
+
 uint32_t br_queue_items(const Geometry &G, uint32_t accs) { return G.N > 1024 ? accs : (accs + 3) / 4; }
 
 hipError_t br_queue_slots(const BrJobDesc *jobs, int njobs, uint32_t *items)
@@ -2139,15 +2148,6 @@ hipError_t br_queue_slots(const BrJobDesc *jobs, int njobs, uint32_t *items)
     }
     *items = best;
     return hipSuccess;
-}
-
-bool br_mfma_supported(const Geometry &G)
-{
-    const int ch = digit_chunks(G.g_log2B);
-#define X(n_, l_, c_) if (G.N == n_ && G.g_ell == l_ && ch == c_) return true;
-    FDFB_BR_MFMA_CASES(X)
-#undef X
-    return false;
 }
 
 hipError_t launch_br_mfma(const Geometry &G, uint32_t *acc, const uint32_t *ctN, uint32_t A,
