@@ -1615,7 +1615,7 @@ int fdfb_measure_mfma_peak(double *tera_ops, double *ms)
         if (!tera_ops || !ms) return fail(FDFB_EINVAL, "null argument");
         uint32_t blocks = 0;
         K_TRY(fdfbk::mfma_stream_capacity(&blocks));
-        const uint32_t iters = 32768;  // about 40 ms at 3 POPS with every wave slot filled
+        const uint32_t iters = 32768;  // about 25 ms at 4.3 POPS with every wave slot filled
         int32_t *out = nullptr;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         auto done = [&](int rc) {
@@ -1636,7 +1636,7 @@ int fdfb_measure_mfma_peak(double *tera_ops, double *ms)
         if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
         if (e != hipSuccess)
             return done(fail(FDFB_EDEVICE, std::string("mfma calibration: ") + hipGetErrorString(e)));
-        const double ops = (double)blocks * iters * 16 * (16.0 * 16 * 64 * 2);
+        const double ops = (double)blocks * iters * fdfbk::mfma_stream_chains() * (16.0 * 16 * 64 * 2);
         *ms = t;
         *tera_ops = t > 0 ? ops / (t * 1e-3) / 1e12 : 0.0;
         return done(FDFB_OK);

@@ -122,8 +122,10 @@ hipError_t launch_pubmux(const Geometry &G, const uint32_t *rlwe, const uint32_t
                          uint32_t *err, uint32_t *acc, hipStream_t s);
 
 // Calibration stream of independent int8 MFMAs: one 64-thread workgroup per
-// block, 16 chains of iters v_mfma_i32_16x16x64_i8 each; out holds blocks * 64
-// int32.  mfma_stream_capacity gives the workgroups resident at once.
+// block, mfma_stream_chains() chains of iters v_mfma_i32_16x16x64_i8 each; out
+// holds blocks * 64 int32.  mfma_stream_capacity gives the workgroups
+// resident at once.
+uint32_t mfma_stream_chains();
 hipError_t mfma_stream_capacity(uint32_t *blocks);
 hipError_t launch_mfma_stream(uint32_t blocks, uint32_t iters, int32_t *out, hipStream_t s);
 

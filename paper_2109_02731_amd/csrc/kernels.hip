@@ -1653,28 +1653,36 @@ hipError_t launch_init_sign(const Geometry &G, const uint32_t *ctN, uint32_t B, 
 // ---------------------------------------------------------------------------
 // Calibration: a stream of independent int8 MFMAs from registers (no memory
 // traffic, operands with random-looking bytes), to measure the dense int8 rate
-// the device sustains on such data.  Sixteen accumulator chains per wavefront
-// keep the matrix pipe fed; the sums are stored so that nothing is optimised
-// away.
+// the device sustains on such data.  Thirty-two accumulator chains per
+// wavefront, three wavefronts per SIMD, keep the matrix pipe fed; the sums are
+// stored so that nothing is optimised away.  The chains are kept in the
+// architectural registers (two wavefronts per SIMD requested): with them in
+// the accumulation registers the compiler moved chains between registers
+// around the MFMAs, which waited on each other's results and held the pipe at
+// about 72% occupancy instead of 96%.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_mfma_stream(uint32_t iters, int32_t *__restrict__ out)
+constexpr int kStreamChains = 32;
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_mfma_stream(
+    uint32_t iters, int32_t *__restrict__ out)
 {
     // operand bytes spread like random digits and key limbs (a multiplicative hash of the lane)
     const uint32_t h = (blockIdx.x * 64u + threadIdx.x + 1u) * 0x9E3779B1u;
     const v4i a = {(int)h, (int)(h * 0x85EBCA77u), (int)(h * 0xC2B2AE3Du), (int)(h * 0x27D4EB2Fu)};
     const v4i b = {(int)(h ^ 0x165667B1u), (int)(h * 0xD3A2646Cu), (int)(h * 0xFD7046C5u), (int)(h * 0xB55A4F09u)};
-    v4i c[16];
+    v4i c[kStreamChains];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) c[k] = v4i{k, 0, 0, 0};
+    for (int k = 0; k < kStreamChains; ++k) c[k] = v4i{k, 0, 0, 0};
     for (uint32_t it = 0; it < iters; ++it) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) c[k] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c[k], 0, 0, 0);
+        for (int k = 0; k < kStreamChains; ++k) c[k] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c[k], 0, 0, 0);
     }
     int32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) sum += c[k][0] + c[k][1] + c[k][2] + c[k][3];
+    for (int k = 0; k < kStreamChains; ++k) sum += c[k][0] + c[k][1] + c[k][2] + c[k][3];
     out[(size_t)blockIdx.x * 64 + threadIdx.x] = sum;
 }
+
+uint32_t mfma_stream_chains() { return kStreamChains; }
 
 hipError_t mfma_stream_capacity(uint32_t *blocks)
 {
