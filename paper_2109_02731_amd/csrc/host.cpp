@@ -828,7 +828,10 @@ int enqueue_pipeline(const fdfb_job *jobs, uint32_t njobs, const ScratchView *vi
             const uint64_t room = G.N > 1024 ? goal - items : (goal - items) * 4;
             uint32_t take = total - s_next[ks];
             if (take > room) take = (uint32_t)(room / gran * gran);
-            if (!take) break;
+            if (!take) {
+                if (!d.empty()) break;                        // the launch is full to a cut point
+                take = std::min(total - s_next[ks], gran);  // never an empty launch
+            }
             d.push_back(job_desc(j, views[ks], true, s_next[ks], take));
             items += fdfbk::br_queue_items(G, take);
             s_next[ks] += take;
