@@ -326,18 +326,25 @@ __global__ __launch_bounds__(256) void k_pubmux(const uint32_t *__restrict__ rlw
     __syncthreads();
     const uint32_t *R = rlwe + (size_t)b * ellb * 2 * N;
     for (int m = threadIdx.x; m < N; m += blockDim.x) {
-        uint32_t o0 = pa[m], o1 = 0;
+        // each product digit x word mod 2^32 as digit x low half + (digit x high half) << 16:
+        // the digits and the 16-bit halves fit the full-rate signed 24-bit multiplier, and
+        // the two sums recombine exactly mod 2^32
+        uint32_t lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
         for (int i = 0; i < ellb; ++i) {
             const int8_t *d = dx + i * 2 * N + N + m;  // d[-p] = digit at m - p
             const uint32_t *rb = R + (size_t)i * 2 * N, *ra = rb + N;
+#pragma unroll 16
             for (int p = 0; p < N; ++p) {
-                const uint32_t dv = (uint32_t)(int32_t)d[-p];
-                o0 += dv * rb[p];
-                o1 += dv * ra[p];
+                const int dv = d[-p];
+                const uint32_t wb = rb[p], wa = ra[p];
+                lo0 += (uint32_t)__mul24(dv, (int)(wb & 0xFFFFu));
+                hi0 += (uint32_t)__mul24(dv, (int)(wb >> 16));
+                lo1 += (uint32_t)__mul24(dv, (int)(wa & 0xFFFFu));
+                hi1 += (uint32_t)__mul24(dv, (int)(wa >> 16));
             }
         }
-        o[m] = o0;
-        o[N + m] = o1;
+        o[m] = pa[m] + lo0 + (hi0 << 16);
+        o[N + m] = lo1 + (hi1 << 16);
     }
 }
 
