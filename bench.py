@@ -134,12 +134,15 @@ def oracle_timing(threads: int):
     return res
 
 
-def serving_run(fd, torch, W, ctxs, presets, pools, lids, count, rate, max_batch=512, nstreams=3, seed=None):
-    """Poisson request stream through the continuous-batching server.
-    Returns throughput, request latency percentiles and batching counters."""
+def serving_run(fd, torch, W, ctxs, presets, pools, lids, count, rate, max_batch=512, nstreams=3, seed=None,
+                request_max=512):
+    """Poisson request stream through the continuous-batching server
+    (request sizes uniform in 1..request_max; the server forms batches of up
+    to max_batch samples).  Returns throughput, request latency percentiles
+    and batching counters."""
     import threading
     seed = W.ARRIVAL_SEED if seed is None else seed
-    times, sizes, which = W.poisson_arrivals(seed, count, rate, max_batch=max_batch)
+    times, sizes, which = W.poisson_arrivals(seed, count, rate, max_batch=request_max)
     rng = np.random.default_rng(seed + 1)
     reqs = []
     for k in range(count):
@@ -201,9 +204,14 @@ def serving_bench(fd, torch, W, ctx2, count):
         msgs = W.messages(6000 + k, 4096, p.t)
         cts = fd.to_device(c.encrypt_debug(msgs, seed=6100 + k))
         pools.append((cts, [t[msgs] for t in tables]))
-    sat = serving_run(fd, torch, W, ctxs, presets, pools, lids, count, 2000.0)
-    sus = serving_run(fd, torch, W, ctxs, presets, pools, lids, count, 0.8 * sat["requests_per_s"], seed=W.ARRIVAL_SEED + 7)
-    return {"saturated": sat, "sustainable": sus}
+    # the server joins requests of one parameter set into batches of up to
+    # 2048 samples on two streams: a full N = 1024 batch then fills every SIMD
+    # twice in both rotation phases
+    kw = dict(max_batch=2048, nstreams=2)
+    sat = serving_run(fd, torch, W, ctxs, presets, pools, lids, count, 2000.0, **kw)
+    sus = serving_run(fd, torch, W, ctxs, presets, pools, lids, count, 0.8 * sat["requests_per_s"],
+                      seed=W.ARRIVAL_SEED + 7, **kw)
+    return {"saturated": sat, "sustainable": sus, "server": {"max_batch": 2048, "streams": 2, "request_max": 512}}
 
 
 def mixed_bench(fd, torch, W, ctx2, steps: int):
