@@ -195,6 +195,7 @@ def test_every_entry_point_survives_null_and_zero_arguments():
     assert L.fdfb_bootstrap_pipeline(C.byref(plain), 1, 0, nul) == -1
     assert "work-queue" in fd.lib().fdfb_last_error().decode()
     assert L.fdfb_bootstrap_pipeline(C.byref(job), 1, 65, nul) == -1
+    assert L.fdfb_bootstrap_pipeline(nul, 0, 0, nul) == 0  # nothing to do
 
 
 def test_context_lock_serialises_threads():
