@@ -20,6 +20,7 @@
 #include "fdfb.h"
 #include "internal.h"
 #include "kernels.h"
+#include "pipeline_plan.h"
 
 namespace fdfbi {
 
@@ -787,70 +788,29 @@ int enqueue_pipeline(const fdfb_job *jobs, uint32_t njobs, const ScratchView *vi
 {
     // resident workgroups of the persistent kernel for these jobs
     std::vector<fdfbk::BrJobDesc> all;
-    for (uint32_t k = 0; k < njobs; ++k)
+    std::vector<fdfbp::Job> pj(njobs);
+    for (uint32_t k = 0; k < njobs; ++k) {
+        const fdfbk::Geometry &G = jobs[k].ctx->geom;
+        pj[k] = {jobs[k].B, (uint32_t)G.boot_ell, G.N > 1024};
         if (jobs[k].B) all.push_back(job_desc(jobs[k], views[k], false, 0, jobs[k].B));
+    }
     uint32_t cap = 0;
     K_TRY(fdfbk::br_queue_slots(all.data(), (int)all.size(), &cap));
     if (!cap) return FDFB_OK;
-    const uint64_t target = (uint64_t)rounds * cap;
-
-    std::vector<uint32_t> s_next(njobs, 0);  // sign accumulators of each job scheduled so far
-    std::vector<uint32_t> ready;             // jobs whose public mux is enqueued
-    uint32_t ks = 0;                         // first job with sign accumulators left to schedule
     std::vector<fdfbk::BrJobDesc> d;
-    std::vector<uint32_t> f_jobs, s_done;
-    for (;;) {
+    for (const fdfbp::Launch &L : fdfbp::schedule(pj, cap, rounds)) {
+        for (uint32_t k : L.fronts)
+            if (int rc = job_front(jobs[k], views[k], st)) return rc;
         d.clear();
-        f_jobs.clear();
-        s_done.clear();
-        uint64_t items = 0;
-        // function rotations whose inputs are enqueued
-        for (uint32_t k : ready) {
-            d.push_back(job_desc(jobs[k], views[k], false, 0, jobs[k].B));
-            items += fdfbk::br_queue_items(jobs[k].ctx->geom, jobs[k].B);
-            f_jobs.push_back(k);
-        }
-        ready.clear();
-        // then sign rotations of the next jobs, up to whole rounds of the resident capacity
-        const uint64_t goal = std::max(target, (items + cap - 1) / cap * cap);
-        while (ks < njobs && items < goal) {
-            const fdfb_job &j = jobs[ks];
-            if (!j.B) {
-                ++ks;
-                continue;
-            }
-            const fdfbk::Geometry &G = j.ctx->geom;
-            const uint32_t per = G.boot_ell, total = j.B * per;
-            if (s_next[ks] == 0)
-                if (int rc = job_front(j, views[ks], st)) return rc;
-            // cut points: whole samples, and whole items of a narrow geometry
-            const uint32_t gran = G.N > 1024 ? per : std::lcm(4u, per);
-            const uint64_t room = G.N > 1024 ? goal - items : (goal - items) * 4;
-            uint32_t take = total - s_next[ks];
-            if (take > room) take = (uint32_t)(room / gran * gran);
-            if (!take) {
-                if (!d.empty()) break;                        // the launch is full to a cut point
-                take = std::min(total - s_next[ks], gran);  // never an empty launch
-            }
-            d.push_back(job_desc(j, views[ks], true, s_next[ks], take));
-            items += fdfbk::br_queue_items(G, take);
-            s_next[ks] += take;
-            if (s_next[ks] == total) {
-                s_done.push_back(ks);
-                ++ks;
-            }
-        }
-        if (d.empty()) break;
+        for (const fdfbp::Range &r : L.ranges) d.push_back(job_desc(jobs[r.job], views[r.job], r.sign, r.a0, r.A));
         uint32_t launches = 0;
         K_TRY(fdfbk::br_queue_launches(d.data(), (int)d.size(), &launches));
         if (launches > ncounters) return fail(FDFB_EINVAL, "too many job groups for one launch");
         K_TRY(fdfbk::launch_br_queue(d.data(), (int)d.size(), counters, ncounters, st));
-        for (uint32_t k : f_jobs)
+        for (uint32_t k : L.backs)
             if (int rc = job_back(jobs[k], views[k], st)) return rc;
-        for (uint32_t k : s_done) {
+        for (uint32_t k : L.mids)
             if (int rc = job_mid(jobs[k], views[k], st)) return rc;
-            ready.push_back(k);
-        }
     }
     return FDFB_OK;
 }

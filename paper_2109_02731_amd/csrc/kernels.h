@@ -65,11 +65,10 @@ bool br_queue_supported(const Geometry &G);
 hipError_t br_queue_launches(const BrJobDesc *jobs, int njobs, uint32_t *launches);
 hipError_t launch_br_queue(const BrJobDesc *jobs, int njobs, uint32_t *counters, uint32_t ncounters,
                            hipStream_t s);
-// Work items of a job of A accumulators (four per item for a narrow
-// geometry, one for a wide one), and the workgroups of the persistent kernel
-// resident at once for these jobs (each takes one item at a time; the least
-// over the launches the jobs form; 0 when there are none).
-uint32_t br_queue_items(const Geometry &G, uint32_t accs);
+// Workgroups of the persistent kernel resident at once for these jobs (each
+// takes one work item at a time: four accumulators of a narrow geometry or
+// one of a wide one; the least over the launches the jobs form; 0 when there
+// are none).
 hipError_t br_queue_slots(const BrJobDesc *jobs, int njobs, uint32_t *items);
 
 // How one batched blind rotation of the Karatsuba form is issued: the

@@ -2134,8 +2134,6 @@ bool br_mfma_supported(const Geometry &G)
     return false;
 }
 
-uint32_t br_queue_items(const Geometry &G, uint32_t accs) { return G.N > 1024 ? accs : (accs + 3) / 4; }
-
 hipError_t br_queue_slots(const BrJobDesc *jobs, int njobs, uint32_t *items)
 {
     for (int j = 0; j < njobs; ++j)
