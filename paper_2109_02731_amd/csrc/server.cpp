@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "fdfb.h"
+#include "arena.h"
 #include "internal.h"
 
 using fdfbi::fail;
@@ -59,46 +60,6 @@ struct Slot {
     size_t off = 0, bytes = 0;  // the batch's region of the arena
 };
 
-// First-fit allocator over one device block; offsets and sizes are multiples of 256.
-class Arena {
-  public:
-    void reset(size_t size)
-    {
-        free_.clear();
-        if (size) free_[0] = size;
-    }
-    bool alloc(size_t bytes, size_t *off)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            const size_t rest = it->second - bytes;
-            free_.erase(it);
-            if (rest) free_[*off + bytes] = rest;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + bytes == next->first) {
-            bytes += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += bytes;
-                return;
-            }
-        }
-        free_[off] = bytes;
-    }
-
-  private:
-    std::map<size_t, size_t> free_;  // offset -> length of each free range
-};
 
 }  // namespace
 
@@ -107,7 +68,7 @@ struct fdfb_server {
     uint32_t max_batch = 0;
     size_t budget = 0, in_flight = 0, max_in_flight = 0;
     char *arena_base = nullptr;
-    Arena arena;
+    fdfbi::Arena arena;
     std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;

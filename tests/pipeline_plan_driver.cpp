@@ -1,6 +1,6 @@
 // Invariants of the software-pipeline schedule (fdfbp::schedule) over random
 // job mixes; prints "ok" when every case holds.  Built and run by
-// tests/test_pipeline_plan.py on the CPU.
+// tests/test_host_logic.py on the CPU.
 #include <cstdio>
 #include <cstdlib>
 #include <random>
