@@ -482,9 +482,9 @@ def main():
                     help="also time the 784->128->10 circuit this many inferences (0 skips)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (the fixed plan rule issues the blind rotations)")
-    ap.add_argument("--plan-sign", default=None, choices=["auto", "1w", "1w2", "2w", "queue"],
+    ap.add_argument("--plan-sign", default=None, choices=["auto", "1w", "1w2", "2w", "queue", "split"],
                     help="issue the sign rotations with this plan instead of tuning (for profiles)")
-    ap.add_argument("--plan-func", default=None, choices=["auto", "1w", "1w2", "2w", "queue"],
+    ap.add_argument("--plan-func", default=None, choices=["auto", "1w", "1w2", "2w", "queue", "split"],
                     help="issue the function rotation with this plan instead of tuning (for profiles)")
     ap.add_argument("--batch-sweep", type=int, default=0, metavar="STEPS",
                     help="also time the bench configuration at batch 128..4096 this many steps (0 skips)")

@@ -466,6 +466,9 @@ void fdfb_server_destroy(fdfb_server *srv);
  *                    one after another (N = 1024, gadget 2^7 x 3)
  *   FDFB_FORM_2W     two wavefronts per accumulator (N = 1024, gadget 2^7 x 3)
  *   FDFB_FORM_QUEUE  the persistent work-queue kernel, one launch
+ *   FDFB_FORM_SPLIT  eight wavefronts per accumulator instead of four, each
+ *                    with a quarter of one output component's tiles: for
+ *                    rounds too small to fill the device (N = 2048)
  * round: accumulators per launch round (0 = the form's resident capacity;
  * ignored by the queue).  ms: measured milliseconds per rotation (0 if none).
  * Every plan gives the same output bits.
@@ -475,6 +478,7 @@ void fdfb_server_destroy(fdfb_server *srv);
 #define FDFB_FORM_1W2 2u
 #define FDFB_FORM_2W 3u
 #define FDFB_FORM_QUEUE 4u
+#define FDFB_FORM_SPLIT 5u
 typedef struct fdfb_br_plan {
     uint32_t form, round;
     double ms;

@@ -78,7 +78,7 @@ EXPORTED = [
     "fdfb_bootstrap_pipeline",
 ]
 
-FORMS = {0: "auto", 1: "1w", 2: "1w2", 3: "2w", 4: "queue"}
+FORMS = {0: "auto", 1: "1w", 2: "1w2", 3: "2w", 4: "queue", 5: "split"}
 
 DEVERR_LUT_ID = 0x1
 

@@ -78,8 +78,10 @@ hipError_t br_queue_slots(const BrJobDesc *jobs, int njobs, uint32_t *items);
 // or the four-wavefront k_br_kara at N = 2048); kForm1W2 one wavefront per
 // accumulator, two per SIMD (k_br_kara1w2, N = 1024); kForm2W two wavefronts
 // per accumulator (k_br_kara1w2, N = 1024); kFormQueue the persistent
-// work-queue kernel in one launch.
-enum BrForm : uint32_t { kFormAuto = 0, kForm1W = 1, kForm1W2 = 2, kForm2W = 3, kFormQueue = 4 };
+// work-queue kernel in one launch; kFormSplit eight wavefronts per
+// accumulator, each with a quarter of one output component's tiles
+// (k_br_kara with four wavefronts per component, N = 2048).
+enum BrForm : uint32_t { kFormAuto = 0, kForm1W = 1, kForm1W2 = 2, kForm2W = 3, kFormQueue = 4, kFormSplit = 5 };
 struct BrPlan {
     uint32_t form = kFormAuto;
     uint32_t round = 0;

@@ -699,12 +699,14 @@ template <int END> struct StaticFor<END, END> {
     template <class F> __device__ __attribute__((always_inline)) static void run(F &&) {}
 };
 
-template <int N, int ELL, int CH>
+// WPC_: wavefronts per output component (by default 1 up to N = 1024, 2 above;
+// 4 at N = 2048 for the split form of small rounds)
+template <int N, int ELL, int CH, int WPC_ = (N > 1024 ? 2 : 1)>
 struct BrKara {
     static constexpr int M = N / 2;                   // size of the half rings
     static constexpr int RPC = ELL * CH;              // virtual digit rows per component
     static constexpr int RV = 2 * RPC;                // virtual digit rows per CMux
-    static constexpr int WPC = N > 1024 ? 2 : 1;      // wavefronts per output component
+    static constexpr int WPC = WPC_;                  // wavefronts per output component
     static constexpr int WAVES = 2 * WPC;
     static constexpr int NT = M / 64 / WPC;           // output tiles per wavefront and product
     static constexpr int NKB = M / 64;                // k-blocks per product
@@ -747,13 +749,13 @@ __device__ __attribute__((always_inline)) inline void kara_rot4(const uint4 *src
 
 // One accumulator (row, 2N words) rotated by the whole workgroup (64 WAVES
 // threads), its ModSwitched coefficients a_1..a_n at crow; LDS at smem.
-template <int N, int ELL, int CH>
+template <int N, int ELL, int CH, int WPC = BrKara<N, ELL, CH>::WPC>
 __device__ __attribute__((always_inline)) inline void br_kara_run(uint8_t *smem, uint32_t *__restrict__ row,
                                                                  const uint32_t *__restrict__ crow, int n,
                                                                  const v4i *__restrict__ bfrag,
                                                                  const uint32_t *__restrict__ corr, int log2B)
 {
-    using G = BrKara<N, ELL, CH>;
+    using G = BrKara<N, ELL, CH, WPC>;
     constexpr int M = G::M;
     uint32_t *accL = (uint32_t *)smem;  // [2][N]: per component, even half then odd half
     uint32_t *digL = accL + 2 * N;      // [DSETS][RV][3 products][SEQ_WORDS]
@@ -972,8 +974,8 @@ __device__ __attribute__((always_inline)) inline void br_kara_run(uint8_t *smem,
     }
 }
 
-template <int N, int ELL, int CH>
-__global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g,
+template <int N, int ELL, int CH, int WPC = BrKara<N, ELL, CH>::WPC>
+__global__ __launch_bounds__(128 * WPC, 4 / WPC) void k_br_kara(uint32_t *__restrict__ acc_g,
                                                     const uint32_t *__restrict__ ctN, uint32_t a_base,
                                                     uint32_t accs_per_ct, int n,
                                                     const v4i *__restrict__ bfrag,
@@ -981,8 +983,8 @@ __global__ __launch_bounds__(256, 2) void k_br_kara(uint32_t *__restrict__ acc_g
 {
     extern __shared__ uint8_t smem[];
     const uint32_t a_idx = a_base + blockIdx.x;  // accumulator; sample a_idx / accs_per_ct
-    br_kara_run<N, ELL, CH>(smem, acc_g + (size_t)a_idx * 2 * N,
-                            ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1, n, bfrag, corr, log2B);
+    br_kara_run<N, ELL, CH, WPC>(smem, acc_g + (size_t)a_idx * 2 * N,
+                                 ctN + (size_t)(a_idx / accs_per_ct) * (n + 1) + 1, n, bfrag, corr, log2B);
 }
 
 // ---------------------------------------------------------------------------
@@ -1862,6 +1864,7 @@ static constexpr bool br_kara_two()
 struct KaraFit {
     uint32_t cap1 = 0;  // workgroups of br_kara_kernel resident at once
     uint32_t cap2 = 0;  // of k_br_kara1w2<.., 1> (0 when it is not used)
+    uint32_t capS = 0;  // of the split form k_br_kara<.., 4> (N = 2048; 0 otherwise)
     uint32_t round() const { return cap2 > cap1 ? cap2 : cap1; }
 };
 
@@ -1886,6 +1889,9 @@ static hipError_t br_kara_fit(KaraFit *out)
         if (e == hipSuccess)
             e = kernel_capacity(br_kara_kernel<N, ELL, CH>(), br_kara_threads<N, ELL, CH>(), GK::LDS_BYTES, cus,
                                 &f->cap1);
+        if constexpr (GK::WPC == 2)
+            if (e == hipSuccess)
+                e = kernel_capacity((const void *)k_br_kara<N, ELL, CH, 4>, 512, GK::LDS_BYTES, cus, &f->capS);
         if constexpr (br_kara_two<N, ELL, CH>()) {
             if (e == hipSuccess)
                 e = kernel_capacity((const void *)k_br_kara1w2<N, ELL, CH, 1>, 64, GK::LDS2W_BYTES, cus, &f->cap2);
@@ -1905,6 +1911,10 @@ static uint32_t round_form(uint32_t form, uint32_t cnt, const KaraFit &fit)
     if constexpr (br_kara_two<N, ELL, CH>()) {
         if (form == kFormAuto) return cnt > fit.cap1 ? kForm1W2 : (2 * cnt <= fit.cap1 ? kForm2W : kForm1W);
         return form;
+    } else if constexpr (BrKara<N, ELL, CH>::WPC == 2) {
+        // a round that leaves three SIMDs in four without a wavefront splits each accumulator
+        if (form == kFormAuto) return 4 * cnt <= fit.cap1 ? kFormSplit : kForm1W;
+        return form == kFormSplit ? kFormSplit : kForm1W;
     } else {
         return kForm1W;
     }
@@ -1919,6 +1929,7 @@ static uint32_t plan_round(const BrPlan &plan, const KaraFit &fit)
     case kForm1W: return fit.cap1;
     case kForm1W2: return fit.cap2 ? fit.cap2 : fit.cap1;
     case kForm2W: return std::max(1u, fit.cap1 / 2);
+    case kFormSplit: return fit.capS ? fit.capS : fit.cap1;
     default: return fit.round();
     }
 }
@@ -1934,10 +1945,12 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
     // each XCD's L2 once and shared, where a second round started by
     // completions would drift and re-fetch.  A round may begin inside a
     // sample's group of accumulators (a_base), so no round is left short.
-    // The fixed rule (kFormAuto) by round size: more accumulators than one
-    // wavefront per SIMD holds run two wavefronts per SIMD (k_br_kara1w2 with
-    // one wavefront per accumulator); a round that gives every wavefront of
-    // two per accumulator a SIMD runs those; the rest one wavefront per SIMD.
+    // The fixed rule (kFormAuto) by round size: at N = 1024, more accumulators
+    // than one wavefront per SIMD holds run two wavefronts per SIMD
+    // (k_br_kara1w2 with one wavefront per accumulator), a round that gives
+    // every wavefront of two per accumulator a SIMD runs those, the rest one
+    // wavefront per SIMD; at N = 2048 a round of at most a quarter of the
+    // capacity runs the split form (eight wavefronts per accumulator).
     KaraFit fit;
     hipError_t e0 = br_kara_fit<N, ELL, CH>(&fit);
     if (e0 != hipSuccess) return e0;
@@ -1953,6 +1966,10 @@ static hipError_t launch_br_kara_t(const Geometry &G, uint32_t *acc, const uint3
                 hipLaunchKernelGGL((k_br_kara1w2<N, ELL, CH, 2>), dim3(cnt), dim3(128), GK::LDS2W_BYTES, s, acc,
                                    ctN, a0, accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
         }
+        if constexpr (GK::WPC == 2)
+            if (form == kFormSplit)
+                hipLaunchKernelGGL((k_br_kara<N, ELL, CH, 4>), dim3(cnt), dim3(512), GK::LDS_BYTES, s, acc, ctN, a0,
+                                   accs_per_ct, G.n, (const v4i *)brk_frag, corr, G.g_log2B);
         if (form == kForm1W) {
             if constexpr (GK::WPC == 1)
                 hipLaunchKernelGGL((k_br_kara1w<N, ELL, CH>), dim3(cnt), dim3(64), GK::LDS_BYTES, s, acc, ctN, a0,
@@ -2194,13 +2211,14 @@ bool br_plan_valid(const Geometry &G, const BrPlan &plan)
     case kForm1W2:
     case kForm2W: return G.N == 1024 && G.g_ell == 3 && digit_chunks(G.g_log2B) == 1;
     case kFormQueue: return br_queue_supported(G) && plan.round == 0;
+    case kFormSplit: return G.N > 1024;
     default: return false;
     }
 }
 
 int br_plan_candidates(const Geometry &G, BrPlan *out, int max)
 {
-    const BrPlan all[] = {{kFormAuto, 0}, {kForm1W, 0}, {kForm1W2, 0}, {kForm2W, 0}, {kFormQueue, 0}};
+    const BrPlan all[] = {{kFormAuto, 0}, {kForm1W, 0}, {kForm1W2, 0}, {kForm2W, 0}, {kFormQueue, 0}, {kFormSplit, 0}};
     int k = 0;
     KaraFit fit;
     const bool have_fit = fit_of(G, &fit) == hipSuccess;
@@ -2210,7 +2228,7 @@ int br_plan_candidates(const Geometry &G, BrPlan *out, int max)
         ++k;
         // the same form in rounds of half its capacity (more rounds, fewer
         // workgroups walking the key together)
-        if (have_fit && (p.form == kForm1W || p.form == kForm1W2)) {
+        if (have_fit && (p.form == kForm1W || p.form == kForm1W2 || p.form == kFormSplit)) {
             const uint32_t half = plan_round(p, fit) / 2;
             if (half) {
                 if (k < max) out[k] = BrPlan{p.form, half};

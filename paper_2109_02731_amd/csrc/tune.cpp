@@ -80,7 +80,7 @@ int load_locked(const char *path, bool must_exist)
             e.plan.form = form;
             e.plan.round = round;
             e.ms = ms;
-            if (form <= fdfbk::kFormQueue) put(e);
+            if (form <= fdfbk::kFormSplit) put(e);
         }
     }
     std::fclose(f);
