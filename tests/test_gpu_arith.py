@@ -58,3 +58,51 @@ def test_maximum_and_product_c1(oracle_keys_c1):
                 ref = _oracle_chain(oracle_keys_c1, p, np.array([[1, 1], [1, -1]]), stacked, [qs, qd],
                                     np.array([[1, -1]]))
             assert np.array_equal(got[k], ref[0]), (op.__name__, k)
+
+
+def test_crt_arithmetic_c1_all_pairs(oracle_keys_c1):
+    """Z_12 as residues mod 3 and 4 in Z_8: every pair through add, sub and
+    multiply decrypts to the exact result mod 12; two residues of the product
+    path match the same composition on the oracle bit for bit."""
+    p = W.C1
+    t = p.t
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C1"])
+    crt = arith.CRT(ctx, (3, 4))
+    M = crt.M
+    X = np.array([a for a in range(M) for _ in range(M)])
+    Y = np.array([b for _ in range(M) for b in range(M)])
+    cx, cy = crt.encrypt_debug(X, seed=81), crt.encrypt_debug(Y, seed=82)
+    dx, dy = fd.to_device(cx), fd.to_device(cy)
+    outs = {}
+    for name, op, want in (("add", crt.add, (X + Y) % M), ("sub", crt.sub, (X - Y) % M),
+                           ("mul", crt.multiply, (X * Y) % M)):
+        out = op(dx, dy)
+        torch.cuda.synchronize()
+        outs[name] = fd.to_host(out)
+        assert np.array_equal(crt.decrypt_debug(outs[name]), want), name
+    assert ctx.device_errors() == 0
+    # the product's residues of two values through the same steps on the oracle
+    for row in (1, 2 * 77 + 1):
+        i = row % crt.k
+        qs, qd = arith.crt_quarter_tables(t, crt.moduli[i])
+        red = arith.mod_table(t, crt.moduli[i], True)
+        stacked = np.stack([cx[row], cy[row]])
+        q = _oracle_chain(oracle_keys_c1, p, np.array([[1, 1], [1, -1]]), stacked, [qs, qd], np.array([[1, -1]]))
+        ref = oracle.fdfb(oracle_keys_c1, *oracle.setup_polynomial(red, p.N), q[0])
+        assert np.array_equal(outs["mul"][row], ref), row
+
+
+def test_crt_arithmetic_c2_random():
+    """Z_840 as residues mod 3, 5, 7 and 8 in Z_16 at n=630 N=1024: random
+    pairs through add, sub and multiply decrypt to the exact results."""
+    p = W.C2
+    ctx = fd.Context.keygen(p, W.KEY_SEED["C2"])
+    crt = arith.CRT(ctx, (3, 5, 7, 8))
+    rng = np.random.default_rng(840)
+    X, Y = rng.integers(0, crt.M, 48), rng.integers(0, crt.M, 48)
+    dx, dy = fd.to_device(crt.encrypt_debug(X, seed=83)), fd.to_device(crt.encrypt_debug(Y, seed=84))
+    for name, op, want in (("add", crt.add, (X + Y) % crt.M), ("sub", crt.sub, (X - Y) % crt.M),
+                           ("mul", crt.multiply, (X * Y) % crt.M)):
+        out = op(dx, dy)
+        torch.cuda.synchronize()
+        assert np.array_equal(crt.decrypt_debug(fd.to_host(out)), want), name
