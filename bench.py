@@ -47,16 +47,21 @@ def br_ops_per_accumulator(p) -> float:
     return p.n * 4 * p.g_ell * p.N * p.N * 4 * chunks * 2.0
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(src: str = None) -> str:
     """Hash of the blind-rotation kernel's source: the kernel itself and its
-    launcher (other kernels in the same file do not change its traffic)."""
-    with open(os.path.join(ROOT, "paper_2109_02731_amd", "csrc", "kernels.hip")) as f:
-        src = f.read()
+    launcher (other kernels in the same file do not change its traffic),
+    with line comments and blank lines left out."""
+    if src is None:
+        with open(os.path.join(ROOT, "paper_2109_02731_amd", "csrc", "kernels.hip")) as f:
+            src = f.read()
     h = hashlib.sha256()
     for start, end in (("struct BrKara {", "// launchers"),
                        ("static const void *br_kara_kernel()", "bool br_mfma_supported")):
         a = src.index(start)
-        h.update(src[a:src.index(end, a)].encode())
+        for line in src[a:src.index(end, a)].splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

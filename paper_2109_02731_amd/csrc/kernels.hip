@@ -1912,7 +1912,8 @@ static uint32_t round_form(uint32_t form, uint32_t cnt, const KaraFit &fit)
         if (form == kFormAuto) return cnt > fit.cap1 ? kForm1W2 : (2 * cnt <= fit.cap1 ? kForm2W : kForm1W);
         return form;
     } else if constexpr (BrKara<N, ELL, CH>::WPC == 2) {
-        // a round that leaves three SIMDs in four without a wavefront splits each accumulator
+        // a round whose four wavefronts per accumulator would leave at least half of the
+        // SIMDs empty splits each accumulator over eight
         if (form == kFormAuto) return 4 * cnt <= fit.cap1 ? kFormSplit : kForm1W;
         return form == kFormSplit ? kFormSplit : kForm1W;
     } else {
