@@ -463,7 +463,8 @@ def test_blind_rotate_rounds_split_samples(keys_2048):
     may begin inside a sample's group, so every accumulator must still read
     its own sample's row.  Every accumulator equals the rotation with the row
     repeated per accumulator (one per sample); the ones at each round
-    boundary match the oracle bit for bit."""
+    boundary match the oracle bit for bit.  The short last round runs the
+    split form (eight wavefronts per accumulator)."""
     ctx, ok = keys_2048("C3B")
     p = W.C3B
     N = p.N
@@ -483,6 +484,37 @@ def test_blind_rotate_rounds_split_samples(keys_2048):
     got, rep = fd.to_host(d_acc), fd.to_host(d_rep)
     assert np.array_equal(got, rep)
     picks = sorted({0, cap - 2, cap - 1, cap, cap + 1, A - 1})
+    refs = run_oracle_many(lambda k: oracle.blind_rotate(p, ok.brk, ctN[picks[k] // per], acc[picks[k]]),
+                           len(picks))
+    for k, a in enumerate(picks):
+        assert np.array_equal(got[a], refs[k]), a
+
+
+def test_split_form_rounds_inside_samples(keys_2048):
+    """The split form forced in rounds of 100 accumulators at three per sample
+    (every round boundary inside a sample): bit-identical to the default
+    plan, and the accumulators at the boundaries match the oracle."""
+    ctx, ok = keys_2048("C3B")
+    p = W.C3B
+    N = p.N
+    per, A = 3, 210
+    g = np.random.default_rng(38)
+    acc = u32(g, A, 2 * N)
+    ctN = g.integers(0, 2 * N, (A // per, p.n + 1)).astype(np.uint32)
+    say("blind_rotate C3B split form, rounds of 100")
+    ctx.set_plan(A, 5, 100)
+    try:
+        assert ctx.br_launches(A, per) == 3
+        d_split = fd.to_device(acc)
+        ctx.blind_rotate(d_split, fd.to_device(ctN), per, 0)
+    finally:
+        ctx.set_plan(A, None)
+    d_ref = fd.to_device(acc)
+    ctx.blind_rotate(d_ref, fd.to_device(ctN), per, 0)
+    torch.cuda.synchronize()
+    got = fd.to_host(d_split)
+    assert np.array_equal(got, fd.to_host(d_ref))
+    picks = [99, 100, 199, 200, 209]
     refs = run_oracle_many(lambda k: oracle.blind_rotate(p, ok.brk, ctN[picks[k] // per], acc[picks[k]]),
                            len(picks))
     for k, a in enumerate(picks):
