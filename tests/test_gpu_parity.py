@@ -384,6 +384,35 @@ def test_fdfb_c2_full_batch(c2):
     assert np.array_equal(outp, out)
 
 
+def test_fdfb_c2_large_batch_4096(c2):
+    """A batch four times the headline size (8192 sign and 4096 function
+    accumulators, several launch rounds or queue items per phase) with eight
+    tables: every output decrypts to its table's value, the first 1024 rows
+    equal the same samples bootstrapped alone as one batch, and sampled rows
+    from every quarter match the oracle bit for bit."""
+    ctx, ok = c2
+    p = W.C2
+    B = 4096
+    tables = [W.random_lut(W.LUT_SEED["C2"] * 10 + j, p.t) for j in range(8)]
+    lids = np.array([ctx.register_lut(tb) for tb in tables], dtype=np.int32)
+    which = np.random.default_rng(4096).integers(0, 8, B)
+    msgs = W.messages(W.MSG_SEED["C2"] + 9, B, p.t)
+    cts = ctx.encrypt_debug(msgs, seed=W.MSG_SEED["C2"] + 9)
+    say("fdfb C2 batched B=4096, 8 tables")
+    out = _bootstrap(ctx, cts, lids[which], 0, p.n + 1)
+    m, _ = ctx.decrypt_debug(out)
+    assert np.array_equal(m, np.array([tables[w][x] for w, x in zip(which, msgs)]))
+    assert ctx.device_errors() == 0
+    part = _bootstrap(ctx, cts[:1024], lids[which[:1024]], 0, p.n + 1)
+    assert np.array_equal(part, out[:1024])
+    sample = [0, 1500, 2047, 2048, 3100, 4095]
+    rots = {w: oracle.setup_polynomial(tables[w], p.N) for w in set(which[sample].tolist())}
+    say(f"oracle on {len(sample)} samples")
+    refs = run_oracle_many(lambda k: oracle.fdfb(ok, *rots[which[sample[k]]], cts[sample[k]]), len(sample))
+    for k, idx in enumerate(sample):
+        assert np.array_equal(out[idx], refs[k]), idx
+
+
 @pytest.mark.skipif(os.environ.get("FDFB_FULL_PARITY") != "1",
                     reason="all 1024 samples through the oracle take several minutes of host time; "
                            "set FDFB_FULL_PARITY=1 to run")
